@@ -1,0 +1,244 @@
+"""ctypes binding of libfmm_mc.so (argument marshalling only).
+
+Every entry point of ``include/fmm_mc.h`` is reachable under the same name;
+``Chain`` owns one chain's device workspace (a torch uint8 tensor) and
+handle. No computation happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmm_mc.so")
+
+FMM_MC_MIXED = 0x1
+_ERRORS = {0: "ok", -1: "EINVAL", -2: "ERANGE", -3: "ENONNEUTRAL", -4: "ESINGULAR", -5: "ENOMEM",
+           -6: "EDEVICE", -7: "EOVERFLOW", -8: "ESTATE"}
+
+
+class FmmMcError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_ERRORS.get(code, code)} ({code})")
+        self.code = code
+
+
+class RunOpts(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("max_step", ctypes.c_double),
+                ("chain_max_step", ctypes.POINTER(ctypes.c_double)), ("t0", ctypes.c_int64),
+                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("trace_idx", ctypes.c_void_p), ("trace_newpos", ctypes.c_void_p),
+                ("trace_dE", ctypes.c_void_p), ("trace_acc", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64),
+                ("singular", ctypes.c_int64), ("dE_sum", ctypes.c_double),
+                ("energy", ctypes.c_double), ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+SYMBOLS = {
+    "fmm_mc_workspace_bytes": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_uint32,
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "fmm_mc_setup": (ctypes.c_int, [ctypes.POINTER(_vp), _vp, ctypes.c_size_t, _vp, ctypes.c_int64, _dp, _dp,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_uint32]),
+    "fmm_mc_propose": (ctypes.c_int, [_vp, ctypes.c_int64, _dp, _dp]),
+    "fmm_mc_accept": (ctypes.c_int, [_vp, ctypes.c_int64, _dp, _dp, _dp]),
+    "fmm_mc_run": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                                  ctypes.POINTER(RunOpts), ctypes.POINTER(Stats)]),
+    "fmm_mc_replay": (ctypes.c_int, [_vp, ctypes.c_int64, _i64p, _dp, _dp, ctypes.c_double, _dp, _u8p, _i32p]),
+    "fmm_mc_energy": (ctypes.c_int, [_vp, _dp]),
+    "fmm_mc_running_energy": (ctypes.c_int, [_vp, _dp]),
+    "fmm_mc_get_positions": (ctypes.c_int, [_vp, _dp]),
+    "fmm_mc_dump_locals": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "fmm_mc_resetup": (ctypes.c_int, [_vp]),
+    "fmm_mc_destroy": (ctypes.c_int, [_vp]),
+    "fmm_mc_release_tables": (ctypes.c_int, []),
+    "fmm_mc_last_timing": (ctypes.c_int, [_vp, _dp, ctypes.c_int]),
+    "fmm_mc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "fmm_mc_host_operator": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp]),
+}
+
+
+def load_library():
+    """Load libfmm_mc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FmmMcError(-6, f"HIP library missing at {LIB_PATH}; run paper_2006_16622_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SYMBOLS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise FmmMcError(code, what)
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def workspace_bytes(n: int, levels: int, p: int, flags: int = 0) -> int:
+    out = ctypes.c_size_t()
+    _check(load_library().fmm_mc_workspace_bytes(n, levels, p, flags, ctypes.byref(out)), "workspace_bytes")
+    return int(out.value)
+
+
+def host_operator(kind: int, p: int, o=(0, 0, 0)) -> np.ndarray:
+    C = (p + 1) ** 2
+    out = np.zeros(C * C)
+    oo = (ctypes.c_int * 3)(*[int(v) for v in o])
+    _check(load_library().fmm_mc_host_operator(kind, p, oo, _d(out)), "host_operator")
+    return out.reshape(C, C)
+
+
+class Chain:
+    """One Markov chain: positions/charges set up on the GPU (``fmm_mc_setup``)."""
+
+    def __init__(self, pos, q, box: float, levels: int, p: int, flags: int = 0, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        lib = load_library()
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        self.n = len(q)
+        self.levels, self.p, self.box = int(levels), int(p), float(box)
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(self.n, self.levels, self.p, flags)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = _vp()
+        with torch.cuda.device(self.device):
+            rc = lib.fmm_mc_setup(ctypes.byref(self._h), _vp(aligned), nbytes, _vp(self.stream.cuda_stream),
+                                  self.n, _d(pos), _d(q), self.box, self.levels, self.p, flags)
+        _check(rc, "fmm_mc_setup")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().fmm_mc_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def propose(self, idx: int, new_pos) -> float:
+        r = np.ascontiguousarray(new_pos, dtype=np.float64).reshape(3)
+        out = ctypes.c_double()
+        _check(load_library().fmm_mc_propose(self._h, int(idx), _d(r), ctypes.byref(out)), "fmm_mc_propose")
+        return out.value
+
+    def accept(self, idx: int, new_pos, dE=None) -> float:
+        r = np.ascontiguousarray(new_pos, dtype=np.float64).reshape(3)
+        out = ctypes.c_double()
+        dein = ctypes.byref(ctypes.c_double(dE)) if dE is not None else None
+        _check(load_library().fmm_mc_accept(self._h, int(idx), _d(r), dein, ctypes.byref(out)), "fmm_mc_accept")
+        return out.value
+
+    def energy(self) -> float:
+        out = ctypes.c_double()
+        _check(load_library().fmm_mc_energy(self._h, ctypes.byref(out)), "fmm_mc_energy")
+        return out.value
+
+    def running_energy(self) -> float:
+        out = ctypes.c_double()
+        _check(load_library().fmm_mc_running_energy(self._h, ctypes.byref(out)), "fmm_mc_running_energy")
+        return out.value
+
+    def positions(self) -> np.ndarray:
+        out = np.zeros((self.n, 3))
+        _check(load_library().fmm_mc_get_positions(self._h, _d(out)), "fmm_mc_get_positions")
+        return out
+
+    def locals(self, level: int) -> np.ndarray:
+        C = (self.p + 1) ** 2
+        out = np.zeros((8 ** (level - 1), C))
+        _check(load_library().fmm_mc_dump_locals(self._h, int(level), _d(out)), "fmm_mc_dump_locals")
+        return out
+
+    def resetup(self):
+        _check(load_library().fmm_mc_resetup(self._h), "fmm_mc_resetup")
+
+    def replay(self, idx, new_pos, u, beta: float):
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        new_pos = np.ascontiguousarray(new_pos, dtype=np.float64).reshape(-1, 3)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        m = len(idx)
+        dE = np.zeros(m)
+        acc = np.zeros(m, dtype=np.uint8)
+        leaf = np.zeros(m, dtype=np.int32)
+        _check(load_library().fmm_mc_replay(self._h, m, idx.ctypes.data_as(_i64p), _d(new_pos), _d(u),
+                                            float(beta), _d(dE), acc.ctypes.data_as(_u8p),
+                                            leaf.ctypes.data_as(_i32p)), "fmm_mc_replay")
+        return dE, acc.astype(bool), leaf
+
+    def last_timing(self):
+        out = np.zeros(4)
+        _check(load_library().fmm_mc_last_timing(self._h, _d(out), 4), "fmm_mc_last_timing")
+        return out
+
+
+def run_chains(chains, steps: int, seed: int, beta: float, max_step, t0: int = 0, mode: int = 0,
+               traces: bool = False):
+    """fmm_mc_run over a list of Chain objects (same device and stream).
+    With traces, device buffers (torch) are allocated and returned as numpy."""
+    import torch
+    lib = load_library()
+    nc = len(chains)
+    hs = (_vp * nc)(*[c.handle for c in chains])
+    ms = np.ascontiguousarray(np.broadcast_to(np.asarray(max_step, dtype=np.float64), (nc,)))
+    opts = RunOpts()
+    opts.beta = float(beta)
+    opts.max_step = float(ms[0])
+    opts.chain_max_step = _d(ms)
+    opts.t0 = int(t0)
+    opts.mode = int(mode)
+    tr = None
+    if traces:
+        dev = chains[0].device
+        tr = dict(idx=torch.zeros(nc * steps, dtype=torch.int64, device=dev),
+                  newpos=torch.zeros(nc * steps * 3, dtype=torch.float64, device=dev),
+                  dE=torch.zeros(nc * steps, dtype=torch.float64, device=dev),
+                  acc=torch.zeros(nc * steps, dtype=torch.uint8, device=dev))
+        opts.trace_idx = tr["idx"].data_ptr()
+        opts.trace_newpos = tr["newpos"].data_ptr()
+        opts.trace_dE = tr["dE"].data_ptr()
+        opts.trace_acc = tr["acc"].data_ptr()
+    stats = (Stats * nc)()
+    rc = lib.fmm_mc_run(hs, nc, int(steps), int(seed), ctypes.byref(opts), stats)
+    _check(rc, "fmm_mc_run")
+    out = [dict(proposed=s.proposed, accepted=s.accepted, singular=s.singular, dE_sum=s.dE_sum,
+                energy=s.energy, status=s.status) for s in stats]
+    if traces:
+        torch.cuda.synchronize(chains[0].device)
+        tr = {k: v.cpu().numpy() for k, v in tr.items()}
+        tr["newpos"] = tr["newpos"].reshape(nc, steps, 3)
+        for k in ("idx", "dE", "acc"):
+            tr[k] = tr[k].reshape(nc, steps)
+        tr["acc"] = tr["acc"].astype(bool)
+        return out, tr
+    return out

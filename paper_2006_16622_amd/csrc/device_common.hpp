@@ -1,0 +1,210 @@
+// device_common.hpp -- device-side data structures and building blocks of the
+// multilevel Monte Carlo path: solid harmonics by a Cartesian recurrence,
+// Philox4x64-10, exact-rounding wrap/locate, and workgroup reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fmmdev {
+
+constexpr int NT = 256;       // threads per workgroup of every kernel
+constexpr int MAXL = 8;       // levels (depth 7)
+constexpr int NEAR = 27;      // leaf cells of a near region (Alg. 1)
+
+// Constant tables shared by every chain of one degree p on one device.
+struct Tabs {
+  int p, C, Cs;                 // degree, coefficients, padded stride
+  const double *rec;            // [3*Cs]: A_slot, B_slot (recurrence), diag[m]
+  const double *wl2p;           // [Cs] weights of the real-layout L2P: 1, 2 (Re), -2 (Im)
+  const double *wdot;           // [Cs] weights of the bilinear form E.H: 1, 2, 2
+  const double *sgnc;           // [Cs] +1 for m >= 0 slots, -1 for m < 0 (conjugation)
+  const int8_t *il_off;         // [8*189*3]
+  const int16_t *il_id;         // [8*189] offset id in 0..315
+  const double *m2l;            // [316][C in][Cs out]
+  const float *m2l32;           // same in FP32 (mixed precision)
+  const double *m2m;            // [8][C in][Cs out]
+  const int *lat_row;           // CSR of the lattice operator, rows = output slots
+  const int *lat_col;
+  const double *lat_val;
+  double self_const;            // 6 + 8/sqrt3 + 12/sqrt2
+};
+
+// Per-chain device state, carved out of the caller's workspace.
+struct Chain {
+  int N, d, L, B;               // charges, depth, levels (d+1), bin capacity
+  int mixed;
+  double a;                     // box side
+  double *px, *py, *pz, *pq;    // particles by id (wrapped positions)
+  int *leaf_of, *slot_of;
+  int *bin_cnt, *bin_id;        // [nleaf], [nleaf*B]
+  double4 *bin_p;               // [nleaf*B] x, y, z, q
+  double *Ld;                   // scaled local expansions, levels 2..L, cell-major, stride Cs
+  double *Mp;                   // scaled multipoles, levels 1..L (setup)
+  long long ld_off[MAXL + 2];   // offset (in doubles) of level l in Ld
+  long long mp_off[MAXL + 2];
+  double *K, *H;                // lattice moments (scaled by a) and H = R(K)
+  double *dip;                  // [3]
+  double *U;                    // [2]: running energy, setup energy
+  int *status;                  // [4]: error code, overflow, singular count
+  double *scratch;              // small scratch: [0] dE of the single-call propose
+  double *mbox;                 // cross-workgroup mailbox (single-chain run)
+  unsigned *sync;               // [4] sequence / done counters
+  double *red;                  // partial sums of reductions
+  double *stage;                // raw host positions (3N) then charges (N)
+};
+
+__device__ __forceinline__ int cslot(int n, int m) { return n * n + n + m; }
+
+// ------------------------------------------------------------------ rounding
+// Wrap into [0, a): x - a floor(x/a), a result equal to a (or below 0 by
+// rounding) becomes 0. FMA contraction is off in this function and in the
+// displacement arithmetic below (plain operators under the pragma; the
+// __d*_rn helpers are plain operators too and would be contracted): each
+// operation rounds once, as IEEE double arithmetic without contraction does
+// on the host.
+__device__ __forceinline__ double wrap_coord(double x, double a) {
+#pragma clang fp contract(off)
+  double k = floor(x / a);
+  double ak = a * k;
+  double w = x - ak;
+  if (w >= a) w = 0.0;
+  if (w < 0.0) w = 0.0;
+  return w;
+}
+
+// floor(x * (n/a)) clamped to [0, n-1]; a point on a face goes to the upper cell
+__device__ __forceinline__ int cell_coord(double x, double a, int n) {
+#pragma clang fp contract(off)
+  double inv = (double)n / a;
+  int i = (int)floor(x * inv);
+  return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+}
+
+// ------------------------------------------------------------------ Philox4x64-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11)
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    uint64_t y0 = hi1 ^ c[1] ^ k0, y2 = hi0 ^ c[3] ^ k1;
+    c[0] = y0;
+    c[1] = lo1;
+    c[2] = y2;
+    c[3] = lo0;
+  }
+}
+
+// (idx, delta, u) of Metropolis-Hastings step `step` of chain `chain`
+__device__ __forceinline__ void mh_draw(uint64_t seed, uint64_t chain, uint64_t step, int64_t N,
+                                        double D, int64_t &idx, double delta[3], double &u) {
+#pragma clang fp contract(off)
+  uint64_t w[4] = {step, 0, 0, 0}, v[4] = {step, 1, 0, 0};
+  philox4x64_10(w, seed, chain);
+  philox4x64_10(v, seed, chain);
+  idx = (int64_t)__umul64hi(w[0], (uint64_t)N);
+  const double two53 = 1.0 / 9007199254740992.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double f = (double)(w[k + 1] >> 11) * two53;
+    double two_f = 2.0 * f;
+    double centred = two_f - 1.0;
+    delta[k] = D * centred;
+  }
+  u = (double)(v[0] >> 11) * two53;
+}
+
+// ------------------------------------------------------------------ harmonics
+// One group of GS lanes evaluates, for one point x (already divided by the
+// cell size), the table of T_n^m(x) = |x|^n Y_n^m(x^), n <= p: lane m runs
+// the recurrence down column m (diagonal T_m^m by repeated multiplication
+// with (x + i y), then the three-term recurrence in n). The result goes to
+// the real-layout buffer buf (C doubles) as
+//   kind 0 (regular):         buf[n,m] = c Re T,         buf[n,-m] = c Im T
+//   kind 1 (conj. regular):   buf[n,m] = c Re T,         buf[n,-m] = -c Im T
+//   kind 2 (conj. irregular): buf[n,m] = c Re T / r^2n+1, buf[n,-m] = -c Im T / r^2n+1
+// (kind 1 is the P2M term q |s|^n Y_n^{-m}, kind 2 the P2L term
+// q |s|^-(n+1) Y_n^{-m} of Alg. L.2). With acc the values are added.
+template <int GS>
+__device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, double x, double y,
+                                                double z, int kind, double c, bool acc,
+                                                double *buf) {
+  const int p = tb.p;
+  const double *A = tb.rec, *Bc = tb.rec + tb.Cs, *dg = tb.rec + 2 * tb.Cs;
+  for (int m = lane; m <= p; m += GS) {
+    double r2 = x * x + y * y + z * z;
+    double tr = 1.0, ti = 0.0;
+    double inv_r2 = 0.0, s = 1.0;
+    if (kind == 2) {
+      inv_r2 = 1.0 / r2;
+      s = sqrt(inv_r2);
+    }
+    for (int i = 1; i <= m; ++i) {
+      double d = dg[i];
+      double nr = (tr * x - ti * y) * d;
+      double ni = (tr * y + ti * x) * d;
+      tr = nr;
+      ti = ni;
+      if (kind == 2) s *= inv_r2;
+    }
+    double pr = 0.0, pi = 0.0;  // T_{n-2}
+    double im_sign = (kind == 0) ? 1.0 : -1.0;
+    for (int n = m; n <= p; ++n) {
+      if (n > m) {
+        int sl = cslot(n, m);
+        double a = A[sl] * z, b = Bc[sl] * r2;
+        double nr = a * tr - b * pr;
+        double ni = a * ti - b * pi;
+        pr = tr;
+        pi = ti;
+        tr = nr;
+        ti = ni;
+        if (kind == 2) s *= inv_r2;
+      }
+      double f = c * s;
+      int sp = cslot(n, m);
+      if (acc)
+        buf[sp] += f * tr;
+      else
+        buf[sp] = f * tr;
+      if (m > 0) {
+        int sn = cslot(n, -m);
+        if (acc)
+          buf[sn] += im_sign * f * ti;
+        else
+          buf[sn] = im_sign * f * ti;
+      }
+    }
+  }
+}
+
+// sum over the GS lanes of a group (lanes of one wavefront)
+template <int GS>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GS);
+  return v;
+}
+
+// deterministic workgroup sum (fixed tree); red: NT doubles of LDS
+__device__ __forceinline__ double wg_sum(double v, double *red) {
+  int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace fmmdev

@@ -1,0 +1,808 @@
+// fmm_mc.hip -- host side and C ABI of the MI355X library for Metropolis-
+// Hastings Monte Carlo of point charges with the multilevel local-expansion
+// method (Saunders, Grant & Mueller, arXiv:2006.16622). See include/fmm_mc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/fmm_mc.h"
+#include "device_common.hpp"
+#include "host_ops.hpp"
+#include "mc_step.hpp"
+#include "run_kernels.hpp"
+#include "setup_kernels.hpp"
+
+using namespace fmmdev;
+
+namespace {
+
+constexpr int PMAX = 24;
+constexpr int LEVELS_MAX = 7;
+
+int pad_cs(int C) { return (C + 15) / 16 * 16; }
+int group_size(int p) { return p + 1 <= 16 ? 16 : 32; }
+
+struct DevTables {
+  int device = -1, p = -1;
+  Tabs tabs{};
+  std::vector<void *> allocs;
+};
+
+std::mutex g_mu;
+std::vector<DevTables *> g_tables;
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    hipError_t e_ = (x);                           \
+    if (e_ != hipSuccess) return FMM_MC_EDEVICE;   \
+  } while (0)
+
+template <typename T>
+int upload(DevTables *dt, const std::vector<T> &v, const T **out) {
+  void *p = nullptr;
+  size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+  HIPCHK(hipMalloc(&p, bytes));
+  dt->allocs.push_back(p);
+  if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = (const T *)p;
+  return 0;
+}
+
+// Build the constant tables of degree p on the current device.
+int build_tables(int p, DevTables **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  for (auto *t : g_tables)
+    if (t->device == dev && t->p == p) {
+      *out = t;
+      return 0;
+    }
+  auto *dt = new DevTables();
+  dt->device = dev;
+  dt->p = p;
+  const int C = (p + 1) * (p + 1), Cs = pad_cs(C);
+  Tabs &tb = dt->tabs;
+  tb.p = p;
+  tb.C = C;
+  tb.Cs = Cs;
+  // recurrence constants: A(n,m) = (2n-1)/sqrt(n^2-m^2), B(n,m) =
+  // sqrt(((n-1)^2-m^2)/(n^2-m^2)) at slot(n,m); diag(m) = sqrt((2m-1)/(2m))
+  std::vector<double> rec(3 * Cs, 0.0), wl2p(Cs, 0.0), wdot(Cs, 0.0), sgnc(Cs, 0.0);
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m < n; ++m) {
+      int s = fmmhost::slot(n, m);
+      rec[s] = (2.0 * n - 1.0) / std::sqrt(double(n * n - m * m));
+      rec[Cs + s] = std::sqrt(double((n - 1) * (n - 1) - m * m) / double(n * n - m * m));
+    }
+  for (int m = 1; m <= p; ++m) rec[2 * Cs + m] = std::sqrt((2.0 * m - 1.0) / (2.0 * m));
+  for (int n = 0; n <= p; ++n)
+    for (int m = -n; m <= n; ++m) {
+      int s = fmmhost::slot(n, m);
+      wl2p[s] = m == 0 ? 1.0 : (m > 0 ? 2.0 : -2.0);
+      wdot[s] = m == 0 ? 1.0 : 2.0;
+      sgnc[s] = m < 0 ? -1.0 : 1.0;
+    }
+  fmmhost::ILTables il = fmmhost::build_il();
+  // level-independent M2L operators of the 316 distinct offsets
+  std::vector<double> m2l((size_t)316 * C * Cs, 0.0), tmp((size_t)C * C);
+  std::vector<float> m2l32((size_t)316 * C * Cs, 0.0f);
+  for (int id = 0; id < 316; ++id) {
+    int o[3] = {il.distinct[3 * id], il.distinct[3 * id + 1], il.distinct[3 * id + 2]};
+    fmmhost::m2l_operator(p, o, tmp.data());
+    for (int s = 0; s < C; ++s)
+      for (int j = 0; j < C; ++j) {
+        double v = tmp[(size_t)s * C + j];
+        m2l[((size_t)id * C + s) * Cs + j] = v;
+        m2l32[((size_t)id * C + s) * Cs + j] = (float)v;
+      }
+  }
+  std::vector<double> m2m((size_t)8 * C * Cs, 0.0);
+  for (int oc = 0; oc < 8; ++oc) {
+    fmmhost::m2m_operator(p, oc, tmp.data());
+    for (int s = 0; s < C; ++s)
+      for (int j = 0; j < C; ++j) m2m[((size_t)oc * C + s) * Cs + j] = tmp[(size_t)s * C + j];
+  }
+  std::vector<double> lat((size_t)C * C);
+  fmmhost::lattice_operator(p, lat.data());
+  std::vector<int> row(C + 1, 0), col;
+  std::vector<double> val;
+  for (int j = 0; j < C; ++j) {
+    for (int s = 0; s < C; ++s) {
+      double v = lat[(size_t)j * C + s];
+      if (v != 0.0) {
+        col.push_back(s);
+        val.push_back(v);
+      }
+    }
+    row[j + 1] = (int)col.size();
+  }
+  int rc = 0;
+  rc |= upload(dt, rec, &tb.rec);
+  rc |= upload(dt, wl2p, &tb.wl2p);
+  rc |= upload(dt, wdot, &tb.wdot);
+  rc |= upload(dt, sgnc, &tb.sgnc);
+  rc |= upload(dt, il.off, &tb.il_off);
+  rc |= upload(dt, il.off_id, &tb.il_id);
+  rc |= upload(dt, m2l, &tb.m2l);
+  rc |= upload(dt, m2l32, &tb.m2l32);
+  rc |= upload(dt, m2m, &tb.m2m);
+  rc |= upload(dt, row, &tb.lat_row);
+  rc |= upload(dt, col, &tb.lat_col);
+  rc |= upload(dt, val, &tb.lat_val);
+  tb.self_const = 6.0 + 8.0 / std::sqrt(3.0) + 12.0 / std::sqrt(2.0);
+  if (rc) {
+    for (void *a : dt->allocs) (void)hipFree(a);
+    delete dt;
+    return FMM_MC_EDEVICE;
+  }
+  g_tables.push_back(dt);
+  *out = dt;
+  return 0;
+}
+
+// ------------------------------------------------------------------ layout
+struct Layout {
+  size_t off[32];
+  size_t total;
+  int B;
+};
+
+enum {
+  O_PX, O_PY, O_PZ, O_PQ, O_LEAF, O_SLOT, O_BCNT, O_BID, O_BP, O_LD, O_MP, O_K, O_H,
+  O_DIP, O_U, O_STATUS, O_SCRATCH, O_MBOX, O_SYNC, O_RED, O_STAGE, O_STATS, O_CHAIN, O_END
+};
+
+int bin_capacity(int64_t n, int levels) {
+  double nleaf = std::pow(8.0, levels);
+  double mean = double(n) / nleaf;
+  int want = (int)std::ceil(3.0 * mean + 16.0);
+  int B = 16;
+  while (B < want) B *= 2;
+  return B;
+}
+
+void make_layout(int64_t n, int levels, int p, Layout &ly) {
+  const int C = (p + 1) * (p + 1), Cs = pad_cs(C), L = levels + 1;
+  const int64_t nleaf = 1LL << (3 * levels);
+  int64_t ncell_ld = 0, ncell_mp = 0;
+  for (int l = 1; l <= L; ++l) {
+    int64_t c = 1LL << (3 * (l - 1));
+    ncell_mp += c;
+    if (l >= 2) ncell_ld += c;
+  }
+  ly.B = bin_capacity(n, levels);
+  size_t sz[O_END];
+  sz[O_PX] = sz[O_PY] = sz[O_PZ] = sz[O_PQ] = 8 * n;
+  sz[O_LEAF] = sz[O_SLOT] = 4 * n;
+  sz[O_BCNT] = 4 * nleaf;
+  sz[O_BID] = 4 * nleaf * ly.B;
+  sz[O_BP] = 32 * nleaf * ly.B;
+  sz[O_LD] = 8 * ncell_ld * Cs;
+  sz[O_MP] = 8 * ncell_mp * Cs;
+  sz[O_K] = sz[O_H] = 8 * Cs;
+  sz[O_DIP] = 8 * 4;
+  sz[O_U] = 8 * 4;
+  sz[O_STATUS] = 4 * 8;
+  sz[O_SCRATCH] = 8 * 64;
+  sz[O_MBOX] = 8 * 64;
+  sz[O_SYNC] = 4 * 64;
+  const int NG = NT / group_size(p);
+  sz[O_RED] = 8 * ((n + NG - 1) / NG + 64);
+  sz[O_STAGE] = 8 * 4 * n;
+  sz[O_STATS] = 8 * 64;
+  sz[O_CHAIN] = sizeof(Chain);
+  size_t o = 0;
+  for (int i = 0; i < O_END; ++i) {
+    ly.off[i] = o;
+    o += (sz[i] + 255) / 256 * 256;
+  }
+  ly.total = o;
+}
+
+}  // namespace
+
+struct fmm_mc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t n = 0;
+  int levels = 0, p = 0, C = 0, Cs = 0, GS = 16;
+  uint32_t flags = 0;
+  double box = 1.0;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout ly{};
+  Chain ch{};
+  Chain *d_chain = nullptr;
+  DevTables *tables = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  double last_ms[4] = {0, 0, 0, 0};
+  bool ready = false;
+};
+
+namespace {
+
+size_t smem_bytes(int GS, int Cs) {
+  return GS == 16 ? Smem<16>::bytes(Cs) : Smem<32>::bytes(Cs);
+}
+
+int grid_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+int run_setup_kernels(fmm_mc_ctx *h) {
+  Chain &ch = h->ch;
+  const Tabs &tb = h->tables->tabs;
+  hipStream_t st = h->stream;
+  const int L = ch.L;
+  const long long nleaf = 1LL << (3 * h->levels);
+  const size_t shm = smem_bytes(h->GS, h->Cs);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nleaf, NT)), dim3(NT), 0, st, ch.bin_cnt, 0, nleaf);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, ch.status, 0, 8);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, (int *)ch.sync, 0, 64);
+  hipLaunchKernelGGL(k_stage, dim3(grid_for(h->n, NT)), dim3(NT), 0, st, ch);
+  hipLaunchKernelGGL(k_bin_finalize, dim3(grid_for(nleaf, NT)), dim3(NT), 0, st, ch, (int)nleaf);
+  const int NG = NT / h->GS;
+  if (h->GS == 16)
+    hipLaunchKernelGGL(k_p2m_leaf<16>, dim3(grid_for(nleaf, NG)), dim3(NT), shm, st, ch, tb, (int)nleaf);
+  else
+    hipLaunchKernelGGL(k_p2m_leaf<32>, dim3(grid_for(nleaf, NG)), dim3(NT), shm, st, ch, tb, (int)nleaf);
+  for (int l = L - 1; l >= 1; --l)
+    hipLaunchKernelGGL(k_m2m, dim3(1 << (3 * (l - 1))), dim3(NT), 0, st, ch, tb, l);
+  HIPCHK(hipEventRecord(h->ev1, st));
+  for (int l = 2; l <= L; ++l) {
+    int n = 1 << (l - 1), half = n / 2;
+    int ntgt = half * half * half;
+    dim3 grid(grid_for(ntgt, 64), grid_for(h->C, 64), 8);
+    hipLaunchKernelGGL(k_m2l_f64, grid, dim3(NT), 0, st, ch, tb, l);
+  }
+  HIPCHK(hipEventRecord(h->ev2, st));
+  hipLaunchKernelGGL(k_lattice_init, dim3(1), dim3(NT), 0, st, ch, tb);
+  HIPCHK(hipGetLastError());
+  int status[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(status, ch.status, sizeof(status), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, h->ev1, h->ev2));
+  h->last_ms[1] = ms;
+  if (status[1]) return FMM_MC_EOVERFLOW;
+  return 0;
+}
+
+int compute_energy(fmm_mc_ctx *h, double *U) {
+  Chain &ch = h->ch;
+  const Tabs &tb = h->tables->tabs;
+  const int NG = NT / h->GS;
+  const int nb = grid_for(h->n, NG);
+  const size_t shm = (size_t)NG * h->Cs * sizeof(double);
+  if (h->GS == 16)
+    hipLaunchKernelGGL(k_energy<16>, dim3(nb), dim3(NT), shm, h->stream, ch, tb);
+  else
+    hipLaunchKernelGGL(k_energy<32>, dim3(nb), dim3(NT), shm, h->stream, ch, tb);
+  HIPCHK(hipGetLastError());
+  std::vector<double> part(nb), K(h->C), H(h->C), dip(3);
+  HIPCHK(hipMemcpyAsync(part.data(), ch.red, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(K.data(), ch.K, h->C * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(H.data(), ch.H, h->C * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(dip.data(), ch.dip, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double u = 0.0;
+  for (double v : part) u += v;
+  // far lattice 1/2 E.H (weighted real form, scaled by 1/a) and the tin-foil term
+  double eh = 0.0;
+  for (int n = 0; n <= h->p; ++n)
+    for (int m = -n; m <= n; ++m) {
+      int s = n * n + n + m;
+      eh += (m == 0 ? 1.0 : 2.0) * K[s] * H[s];
+    }
+  const double a = h->box;
+  u += 0.5 * eh / a;
+  u += -2.0 * M_PI / (3.0 * a * a * a) * (dip[0] * dip[0] + dip[1] * dip[1] + dip[2] * dip[2]);
+  *U = u;
+  return 0;
+}
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+}  // namespace
+
+extern "C" {
+
+int fmm_mc_workspace_bytes(int64_t n, int levels, int p, uint32_t flags, size_t *bytes) {
+  (void)flags;
+  if (!bytes || n < 2 || levels < 1 || levels > LEVELS_MAX || p < 0 || p > PMAX) return FMM_MC_EINVAL;
+  Layout ly;
+  make_layout(n, levels, p, ly);
+  *bytes = ly.total;
+  return FMM_MC_OK;
+}
+
+int fmm_mc_setup(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_stream, int64_t n,
+                 const double *pos, const double *q, double box, int levels, int p, uint32_t flags) {
+  if (!out || !dev_ws || !pos || !q) return FMM_MC_EINVAL;
+  if (n < 2 || n > (int64_t)1 << 30 || levels < 1 || levels > LEVELS_MAX || p < 0 || p > PMAX)
+    return FMM_MC_EINVAL;
+  if (!(box > 0.0) || !std::isfinite(box)) return FMM_MC_EINVAL;
+  if (((uintptr_t)dev_ws) % 256) return FMM_MC_EINVAL;
+  double qs = 0.0, qa = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!finite3(pos + 3 * i) || !std::isfinite(q[i])) return FMM_MC_EINVAL;
+    qs += q[i];
+    qa += std::fabs(q[i]);
+  }
+  if (std::fabs(qs) > 1e-12 * qa) return FMM_MC_ENONNEUTRAL;
+  Layout ly;
+  make_layout(n, levels, p, ly);
+  if (ws_bytes < ly.total) return FMM_MC_ENOMEM;
+  auto *h = new (std::nothrow) fmm_mc_ctx();
+  if (!h) return FMM_MC_ENOMEM;
+  int rc = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    rc = build_tables(p, &h->tables);
+  }
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return FMM_MC_EDEVICE;
+  }
+  h->stream = (hipStream_t)hip_stream;
+  h->n = n;
+  h->levels = levels;
+  h->p = p;
+  h->C = (p + 1) * (p + 1);
+  h->Cs = pad_cs(h->C);
+  h->GS = group_size(p);
+  h->flags = flags;
+  h->box = box;
+  h->ws = (char *)dev_ws;
+  h->ws_bytes = ws_bytes;
+  h->ly = ly;
+  Chain &ch = h->ch;
+  char *w = h->ws;
+  ch.N = (int)n;
+  ch.d = levels;
+  ch.L = levels + 1;
+  ch.B = ly.B;
+  ch.mixed = (flags & FMM_MC_MIXED) ? 1 : 0;
+  ch.a = box;
+  ch.px = (double *)(w + ly.off[O_PX]);
+  ch.py = (double *)(w + ly.off[O_PY]);
+  ch.pz = (double *)(w + ly.off[O_PZ]);
+  ch.pq = (double *)(w + ly.off[O_PQ]);
+  ch.leaf_of = (int *)(w + ly.off[O_LEAF]);
+  ch.slot_of = (int *)(w + ly.off[O_SLOT]);
+  ch.bin_cnt = (int *)(w + ly.off[O_BCNT]);
+  ch.bin_id = (int *)(w + ly.off[O_BID]);
+  ch.bin_p = (double4 *)(w + ly.off[O_BP]);
+  ch.Ld = (double *)(w + ly.off[O_LD]);
+  ch.Mp = (double *)(w + ly.off[O_MP]);
+  long long o_ld = 0, o_mp = 0;
+  for (int l = 0; l <= MAXL + 1; ++l) {
+    ch.ld_off[l] = 0;
+    ch.mp_off[l] = 0;
+  }
+  for (int l = 1; l <= ch.L; ++l) {
+    long long c = 1LL << (3 * (l - 1));
+    ch.mp_off[l] = o_mp;
+    o_mp += c * h->Cs;
+    if (l >= 2) {
+      ch.ld_off[l] = o_ld;
+      o_ld += c * h->Cs;
+    }
+  }
+  ch.K = (double *)(w + ly.off[O_K]);
+  ch.H = (double *)(w + ly.off[O_H]);
+  ch.dip = (double *)(w + ly.off[O_DIP]);
+  ch.U = (double *)(w + ly.off[O_U]);
+  ch.status = (int *)(w + ly.off[O_STATUS]);
+  ch.scratch = (double *)(w + ly.off[O_SCRATCH]);
+  ch.mbox = (double *)(w + ly.off[O_MBOX]);
+  ch.sync = (unsigned *)(w + ly.off[O_SYNC]);
+  ch.red = (double *)(w + ly.off[O_RED]);
+  ch.stage = (double *)(w + ly.off[O_STAGE]);
+  h->d_chain = (Chain *)(w + ly.off[O_CHAIN]);
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+      hipEventCreate(&h->ev2) != hipSuccess) {
+    delete h;
+    return FMM_MC_EDEVICE;
+  }
+  std::vector<double> stage(4 * n);
+  std::memcpy(stage.data(), pos, sizeof(double) * 3 * n);
+  std::memcpy(stage.data() + 3 * n, q, sizeof(double) * n);
+  if (hipMemcpyAsync(ch.stage, stage.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(h->d_chain, &ch, sizeof(Chain), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+    fmm_mc_destroy(h);
+    return FMM_MC_EDEVICE;
+  }
+  rc = run_setup_kernels(h);
+  if (rc) {
+    fmm_mc_destroy(h);
+    return rc;
+  }
+  double U = 0.0;
+  rc = compute_energy(h, &U);
+  if (rc) {
+    fmm_mc_destroy(h);
+    return rc;
+  }
+  double u2[2] = {U, U};
+  if (hipMemcpyAsync(ch.U, u2, sizeof(u2), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    fmm_mc_destroy(h);
+    return FMM_MC_EDEVICE;
+  }
+  h->ready = true;
+  *out = h;
+  return FMM_MC_OK;
+}
+
+int fmm_mc_resetup(fmm_mc_t h) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  Chain &ch = h->ch;
+  // stage the current positions and charges, then run the full setup again
+  std::vector<double> buf(4 * h->n);
+  HIPCHK(hipMemcpyAsync(buf.data(), ch.px, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(buf.data() + h->n, ch.py, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(buf.data() + 2 * h->n, ch.pz, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(buf.data() + 3 * h->n, ch.pq, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::vector<double> stage(4 * h->n);
+  for (int64_t i = 0; i < h->n; ++i) {
+    stage[3 * i] = buf[i];
+    stage[3 * i + 1] = buf[h->n + i];
+    stage[3 * i + 2] = buf[2 * h->n + i];
+    stage[3 * h->n + i] = buf[3 * h->n + i];
+  }
+  HIPCHK(hipMemcpyAsync(ch.stage, stage.data(), sizeof(double) * 4 * h->n, hipMemcpyHostToDevice, h->stream));
+  double U0[2];
+  HIPCHK(hipMemcpyAsync(U0, ch.U, sizeof(U0), hipMemcpyDeviceToHost, h->stream));
+  int rc = run_setup_kernels(h);
+  if (rc) return rc;
+  double U = 0.0;
+  rc = compute_energy(h, &U);
+  if (rc) return rc;
+  double u2[2] = {U, U0[1]};
+  HIPCHK(hipMemcpyAsync(ch.U, u2, sizeof(u2), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return FMM_MC_OK;
+}
+
+int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (!new_pos || !dE || !finite3(new_pos)) return FMM_MC_EINVAL;
+  if (idx < 0 || idx >= h->n) return FMM_MC_ERANGE;
+  const Tabs &tb = h->tables->tabs;
+  const size_t shm = smem_bytes(h->GS, h->Cs);
+  if (h->GS == 16)
+    hipLaunchKernelGGL(k_propose_one<16>, dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
+                       new_pos[1], new_pos[2]);
+  else
+    hipLaunchKernelGGL(k_propose_one<32>, dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
+                       new_pos[1], new_pos[2]);
+  HIPCHK(hipGetLastError());
+  double r[2];
+  HIPCHK(hipMemcpyAsync(r, h->ch.scratch, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  *dE = r[0];
+  if (r[1] != 0.0) return FMM_MC_ESINGULAR;
+  return FMM_MC_OK;
+}
+
+int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *dE_in, double *dE_out) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (!new_pos || !finite3(new_pos)) return FMM_MC_EINVAL;
+  if (idx < 0 || idx >= h->n) return FMM_MC_ERANGE;
+  double dE = 0.0;
+  if (dE_in) {
+    dE = *dE_in;
+  } else {
+    int rc = fmm_mc_propose(h, idx, new_pos, &dE);
+    if (rc) return rc;
+  }
+  const Tabs &tb = h->tables->tabs;
+  const size_t shm = smem_bytes(h->GS, h->Cs);
+  const int NG = NT / h->GS;
+  const int nb = accept_blocks(h->ch.L, NG);
+  if (h->GS == 16) {
+    hipLaunchKernelGGL(k_accept_blocks<16>, dim3(nb), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
+                       new_pos[1], new_pos[2]);
+    hipLaunchKernelGGL(k_accept_book<16>, dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
+                       new_pos[1], new_pos[2], dE);
+  } else {
+    hipLaunchKernelGGL(k_accept_blocks<32>, dim3(nb), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
+                       new_pos[1], new_pos[2]);
+    hipLaunchKernelGGL(k_accept_book<32>, dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
+                       new_pos[1], new_pos[2], dE);
+  }
+  HIPCHK(hipGetLastError());
+  int status = 0;
+  HIPCHK(hipMemcpyAsync(&status, h->ch.status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (dE_out) *dE_out = dE;
+  return status ? status : FMM_MC_OK;
+}
+
+// shared driver of fmm_mc_run and fmm_mc_replay
+static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t seed, int64_t t0, double beta,
+                      const double *steps_h, int mode, const int64_t *l_idx, const double *l_pos,
+                      const double *l_u, int64_t *tr_idx, double *tr_pos, double *tr_dE, uint8_t *tr_acc,
+                      int32_t *tr_leaf, fmm_mc_stats *stats) {
+  fmm_mc_t h0 = chains[0];
+  for (int c = 0; c < n_chains; ++c) {
+    if (!chains[c] || !chains[c]->ready) return FMM_MC_ESTATE;
+    if (chains[c]->p != h0->p || chains[c]->device != h0->device || chains[c]->stream != h0->stream)
+      return FMM_MC_ESTATE;
+  }
+  hipStream_t st = h0->stream;
+  const Tabs &tb = h0->tables->tabs;
+  const int GS = h0->GS;
+  const size_t shm = smem_bytes(GS, h0->Cs);
+  // device scratch for per-chain parameters: the first chain's workspace
+  // stats area holds max_step (n_chains <= 4096 supported through a
+  // temporary allocation otherwise)
+  double *d_step = nullptr, *d_stats = nullptr;
+  Chain *d_chains = nullptr;
+  int64_t *d_lidx = nullptr;
+  double *d_lpos = nullptr, *d_lu = nullptr;
+  HIPCHK(hipMallocAsync((void **)&d_step, sizeof(double) * n_chains, st));
+  HIPCHK(hipMallocAsync((void **)&d_stats, sizeof(double) * 8 * n_chains, st));
+  HIPCHK(hipMallocAsync((void **)&d_chains, sizeof(Chain) * n_chains, st));
+  std::vector<Chain> hc(n_chains);
+  for (int c = 0; c < n_chains; ++c) hc[c] = chains[c]->ch;
+  HIPCHK(hipMemcpyAsync(d_step, steps_h, sizeof(double) * n_chains, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_chains, hc.data(), sizeof(Chain) * n_chains, hipMemcpyHostToDevice, st));
+  if (l_idx) {
+    HIPCHK(hipMallocAsync((void **)&d_lidx, sizeof(int64_t) * steps, st));
+    HIPCHK(hipMallocAsync((void **)&d_lpos, sizeof(double) * 3 * steps, st));
+    HIPCHK(hipMallocAsync((void **)&d_lu, sizeof(double) * steps, st));
+    HIPCHK(hipMemcpyAsync(d_lidx, l_idx, sizeof(int64_t) * steps, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_lpos, l_pos, sizeof(double) * 3 * steps, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_lu, l_u, sizeof(double) * steps, hipMemcpyHostToDevice, st));
+  }
+  RunParams rp{};
+  rp.steps = steps;
+  rp.t0 = t0;
+  rp.seed = seed;
+  rp.beta = beta;
+  rp.max_step = d_step;
+  rp.list_idx = d_lidx;
+  rp.list_pos = d_lpos;
+  rp.list_u = d_lu;
+  rp.tr_idx = tr_idx;
+  rp.tr_pos = tr_pos;
+  rp.tr_dE = tr_dE;
+  rp.tr_acc = tr_acc;
+  rp.tr_leaf = tr_leaf;
+  rp.stats = d_stats;
+  bool single = (n_chains == 1 && mode != 1);
+  HIPCHK(hipEventRecord(h0->ev0, st));
+  if (single) {
+    const int NG = NT / GS;
+    int G = accept_blocks(h0->ch.L, NG);
+    int ncu = 0, per = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
+    if (GS == 16)
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_run_single<16>, NT, shm));
+    else
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_run_single<32>, NT, shm));
+    int cap = std::max(1, ncu * std::max(per, 1));
+    G = std::max(1, std::min(G, std::min(cap, ncu)));
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 64);
+    Chain chv = h0->ch;
+    void *args[] = {&chv, (void *)&tb, &rp};
+    hipError_t e;
+    if (GS == 16)
+      e = hipLaunchCooperativeKernel((const void *)k_run_single<16>, dim3(G), dim3(NT), args, shm, st);
+    else
+      e = hipLaunchCooperativeKernel((const void *)k_run_single<32>, dim3(G), dim3(NT), args, shm, st);
+    if (e != hipSuccess) return FMM_MC_EDEVICE;
+  } else {
+    if (GS == 16)
+      hipLaunchKernelGGL(k_run_batched<16>, dim3(n_chains), dim3(NT), shm, st, d_chains, tb, rp);
+    else
+      hipLaunchKernelGGL(k_run_batched<32>, dim3(n_chains), dim3(NT), shm, st, d_chains, tb, rp);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(h0->ev1, st));
+  std::vector<double> hs(8 * n_chains);
+  HIPCHK(hipMemcpyAsync(hs.data(), d_stats, sizeof(double) * 8 * n_chains, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipFreeAsync(d_step, st));
+  HIPCHK(hipFreeAsync(d_stats, st));
+  HIPCHK(hipFreeAsync(d_chains, st));
+  if (l_idx) {
+    HIPCHK(hipFreeAsync(d_lidx, st));
+    HIPCHK(hipFreeAsync(d_lpos, st));
+    HIPCHK(hipFreeAsync(d_lu, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, h0->ev0, h0->ev1));
+  h0->last_ms[0] = ms;
+  int rc = FMM_MC_OK;
+  for (int c = 0; c < n_chains; ++c) {
+    double U[2];
+    HIPCHK(hipMemcpy(U, chains[c]->ch.U, sizeof(U), hipMemcpyDeviceToHost));
+    if (stats) {
+      stats[c].proposed = (int64_t)hs[8 * c];
+      stats[c].accepted = (int64_t)hs[8 * c + 1];
+      stats[c].singular = (int64_t)hs[8 * c + 2];
+      stats[c].dE_sum = hs[8 * c + 3];
+      stats[c].energy = U[0];
+      stats[c].status = (int32_t)hs[8 * c + 4];
+    }
+    if ((int)hs[8 * c + 4] != 0) rc = (int)hs[8 * c + 4];
+  }
+  return rc;
+}
+
+int fmm_mc_run(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t seed, const fmm_mc_run_opts *opts,
+               fmm_mc_stats *stats) {
+  if (!chains || n_chains < 1 || steps < 0 || !opts) return FMM_MC_EINVAL;
+  if (!(opts->beta >= 0.0) || !std::isfinite(opts->beta)) return FMM_MC_EINVAL;
+  std::vector<double> st(n_chains);
+  for (int c = 0; c < n_chains; ++c) {
+    st[c] = opts->chain_max_step ? opts->chain_max_step[c] : opts->max_step;
+    if (!(st[c] >= 0.0) || !std::isfinite(st[c])) return FMM_MC_EINVAL;
+  }
+  if (steps == 0) return FMM_MC_OK;
+  return run_chains(chains, n_chains, steps, seed, opts->t0, opts->beta, st.data(), opts->mode, nullptr, nullptr,
+                    nullptr, opts->trace_idx, opts->trace_newpos, opts->trace_dE, opts->trace_acc, nullptr, stats);
+}
+
+int fmm_mc_replay(fmm_mc_t h, int64_t m, const int64_t *idx, const double *new_pos, const double *u, double beta,
+                  double *dE, uint8_t *acc, int32_t *leaf) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (m < 0 || (m > 0 && (!idx || !new_pos || !u))) return FMM_MC_EINVAL;
+  if (m == 0) return FMM_MC_OK;
+  for (int64_t i = 0; i < m; ++i) {
+    if (idx[i] < 0 || idx[i] >= h->n) return FMM_MC_ERANGE;
+    if (!finite3(new_pos + 3 * i) || !std::isfinite(u[i])) return FMM_MC_EINVAL;
+  }
+  double *d_dE = nullptr;
+  uint8_t *d_acc = nullptr;
+  int32_t *d_leaf = nullptr;
+  HIPCHK(hipMallocAsync((void **)&d_dE, sizeof(double) * m, h->stream));
+  HIPCHK(hipMallocAsync((void **)&d_acc, m, h->stream));
+  HIPCHK(hipMallocAsync((void **)&d_leaf, sizeof(int32_t) * m, h->stream));
+  double zero = 0.0;
+  fmm_mc_t hs[1] = {h};
+  int rc = run_chains(hs, 1, m, 0, 0, beta, &zero, 0, idx, new_pos, u, nullptr, nullptr, d_dE, d_acc, d_leaf,
+                      nullptr);
+  if (rc == FMM_MC_OK) {
+    if (dE) HIPCHK(hipMemcpyAsync(dE, d_dE, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
+    if (acc) HIPCHK(hipMemcpyAsync(acc, d_acc, m, hipMemcpyDeviceToHost, h->stream));
+    if (leaf) HIPCHK(hipMemcpyAsync(leaf, d_leaf, sizeof(int32_t) * m, hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(hipFreeAsync(d_dE, h->stream));
+  HIPCHK(hipFreeAsync(d_acc, h->stream));
+  HIPCHK(hipFreeAsync(d_leaf, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return rc;
+}
+
+int fmm_mc_energy(fmm_mc_t h, double *U) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (!U) return FMM_MC_EINVAL;
+  return compute_energy(h, U);
+}
+
+int fmm_mc_running_energy(fmm_mc_t h, double *U) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (!U) return FMM_MC_EINVAL;
+  HIPCHK(hipMemcpyAsync(U, h->ch.U, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return FMM_MC_OK;
+}
+
+int fmm_mc_get_positions(fmm_mc_t h, double *pos) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (!pos) return FMM_MC_EINVAL;
+  std::vector<double> b(3 * h->n);
+  HIPCHK(hipMemcpyAsync(b.data(), h->ch.px, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(b.data() + h->n, h->ch.py, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(b.data() + 2 * h->n, h->ch.pz, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int64_t i = 0; i < h->n; ++i) {
+    pos[3 * i] = b[i];
+    pos[3 * i + 1] = b[h->n + i];
+    pos[3 * i + 2] = b[2 * h->n + i];
+  }
+  return FMM_MC_OK;
+}
+
+int fmm_mc_dump_locals(fmm_mc_t h, int level, double *out) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (!out || level < 2 || level > h->ch.L) return FMM_MC_EINVAL;
+  const long long nc = 1LL << (3 * (level - 1));
+  std::vector<double> b((size_t)nc * h->Cs);
+  HIPCHK(hipMemcpyAsync(b.data(), h->ch.Ld + h->ch.ld_off[level], sizeof(double) * b.size(),
+                        hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  // undo the cell-size scaling: L_n = L^_n / h^{n+1}
+  const double hcell = h->box / double(1 << (level - 1));
+  for (long long c = 0; c < nc; ++c)
+    for (int n = 0; n <= h->p; ++n) {
+      double sc = std::pow(hcell, -(n + 1));
+      for (int m = -n; m <= n; ++m) {
+        int s = n * n + n + m;
+        out[(size_t)c * h->C + s] = b[(size_t)c * h->Cs + s] * sc;
+      }
+    }
+  return FMM_MC_OK;
+}
+
+int fmm_mc_last_timing(fmm_mc_t h, double *out, int nout) {
+  if (!h || !out || nout < 1) return FMM_MC_EINVAL;
+  for (int i = 0; i < nout && i < 4; ++i) out[i] = h->last_ms[i];
+  return FMM_MC_OK;
+}
+
+int fmm_mc_destroy(fmm_mc_t h) {
+  if (!h) return FMM_MC_EINVAL;
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->ev2) (void)hipEventDestroy(h->ev2);
+  delete h;
+  return FMM_MC_OK;
+}
+
+int fmm_mc_release_tables(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  for (size_t i = 0; i < g_tables.size();) {
+    if (g_tables[i]->device == dev) {
+      for (void *a : g_tables[i]->allocs) (void)hipFree(a);
+      delete g_tables[i];
+      g_tables.erase(g_tables.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  return FMM_MC_OK;
+}
+
+const char *fmm_mc_strerror(int code) {
+  switch (code) {
+    case FMM_MC_OK: return "ok";
+    case FMM_MC_EINVAL: return "invalid argument";
+    case FMM_MC_ERANGE: return "particle index out of range";
+    case FMM_MC_ENONNEUTRAL: return "charges do not sum to zero";
+    case FMM_MC_ESINGULAR: return "new position coincides with another charge";
+    case FMM_MC_ENOMEM: return "workspace too small";
+    case FMM_MC_EDEVICE: return "HIP call failed";
+    case FMM_MC_EOVERFLOW: return "leaf cell capacity exceeded";
+    case FMM_MC_ESTATE: return "handle not ready or chains inconsistent";
+    default: return "unknown error";
+  }
+}
+
+// Host-only diagnostic: the constant operators as the library builds them
+// (no device needed). kind 0: M2L operator of IL offset (o[0],o[1],o[2]),
+// element [in s][out j]; kind 1: M2M operator of child octant o[0]; kind 2:
+// lattice operator, element [out j][in s]. out: (p+1)^4 doubles, host.
+int fmm_mc_host_operator(int kind, int p, const int *o, double *out) {
+  if (!out || p < 0 || p > PMAX) return FMM_MC_EINVAL;
+  if (kind == 0) {
+    if (!o) return FMM_MC_EINVAL;
+    fmmhost::m2l_operator(p, o, out);
+  } else if (kind == 1) {
+    if (!o || o[0] < 0 || o[0] > 7) return FMM_MC_EINVAL;
+    fmmhost::m2m_operator(p, o[0], out);
+  } else if (kind == 2) {
+    fmmhost::lattice_operator(p, out);
+  } else {
+    return FMM_MC_EINVAL;
+  }
+  return FMM_MC_OK;
+}
+
+}  // extern "C"
