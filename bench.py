@@ -1,0 +1,238 @@
+"""Benchmark: Metropolis-Hastings steps per second of the multilevel
+local-expansion method on one MI355X.
+
+Workload (default): the jittered rock-salt system of 46^3 = 97336 charges in
+the periodic unit cube, octree depth 5, degree p = 12, beta = 1, displacement
+uniform in [-0.3/46, 0.3/46)^3, one chain, FP64. A step is one whole MH step
+(proposal energy, decision, and on acceptance the O(189 p^2 L) update of the
+interaction-list expansions plus bookkeeping), all inside one persistent
+kernel. The setup (P2M, M2M, M2L, lattice) is timed separately. The batched
+form (256 independent chains of uneven size and depth in one launch) is
+measured in the same run and reported as its aggregate steps/s.
+
+Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def il_offsets():
+    """interaction-list offsets per octant (Sec. 3.1), for byte counting"""
+    out = {}
+    for oc in range(8):
+        c = [(oc >> k) & 1 for k in range(3)]
+        lst = []
+        for oz in range(-2 - c[2], 4 - c[2]):
+            for oy in range(-2 - c[1], 4 - c[1]):
+                for ox in range(-2 - c[0], 4 - c[0]):
+                    if max(abs(ox), abs(oy), abs(oz)) >= 2:
+                        lst.append((ox, oy, oz))
+        out[oc] = np.array(lst)
+    return out
+
+
+def accept_targets(r, rn, box, L, ilo):
+    """distinct stored cells updated by one accepted move (all levels 2..L)"""
+    tot = 0
+    for l in range(2, L + 1):
+        n = 2 ** (l - 1)
+        sets = []
+        for x in (r, rn):
+            c = np.minimum(np.floor(np.asarray(x) * (n / box)).astype(int), n - 1)
+            oc = int(c[0] & 1) | (int(c[1] & 1) << 1) | (int(c[2] & 1) << 2)
+            b = np.mod(c[None, :] + ilo[oc], n)
+            sets.append(b[:, 0] + n * (b[:, 1] + n * b[:, 2]))
+        tot += len(np.union1d(sets[0], sets[1]))
+    return tot
+
+
+def algorithmic_bytes(wl, pos_before, tr_idx, tr_pos, tr_acc, sample=1500):
+    """HBM bytes the method must touch: per proposal the 2d expansion blocks,
+    the near-field records of 2 x 27 leaf cells and the lattice vectors; per
+    accepted move a read and a write of every distinct interaction-list
+    target on every level plus the lattice vectors. Old positions come from
+    a forward replay of the trace from the positions before the timed run."""
+    C = (wl.p + 1) ** 2
+    L = wl.depth + 1
+    mean_leaf = wl.n / 8 ** wl.depth
+    prop = 2 * wl.depth * C * 8 + 2 * 27 * (mean_leaf * 36 + 4) + 2 * C * 8
+    pos = pos_before.copy()
+    ilo = il_offsets()
+    acc_idx = np.nonzero(tr_acc)[0]
+    pick = set(acc_idx[:: max(1, len(acc_idx) // sample)].tolist())
+    targets = []
+    for t in acc_idx:
+        i = int(tr_idx[t])
+        if t in pick:
+            targets.append(accept_targets(pos[i], tr_pos[t], wl.box, L, ilo))
+        pos[i] = tr_pos[t]
+    mean_t = float(np.mean(targets)) if targets else 0.0
+    acc_bytes = mean_t * C * 8 * 2 + 2 * C * 8 * 3
+    return prop, acc_bytes, float(np.mean(tr_acc)), mean_t
+
+
+def cpu_baseline(wl, nu, nprop=600, nacc=120):
+    """The FP64 oracle timed on one host core: proposals and accepts of the
+    same workload timed separately on a state whose expansions are not
+    initialised (their values do not change the per-step cost; the
+    initialisation of 97336 charges is out of reach of one core here), and
+    combined as t_prop + nu t_acc with the acceptance rate of the GPU run."""
+    import oracle as O
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    t0 = time.perf_counter()
+    m = O.Multilevel(wl.pos, wl.q, wl.box, wl.depth, wl.p, setup="none")
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for t in range(nprop):
+        i, d, u = O.draw(wl.seed, 0, t, wl.n, wl.max_step)
+        m.propose(i, wl.pos[i] + d)
+    tp = (time.perf_counter() - t0) / nprop
+    t0 = time.perf_counter()
+    for t in range(nacc):
+        i, d, u = O.draw(wl.seed, 0, t, wl.n, wl.max_step)
+        m.accept(i, wl.pos[i] + d)
+    ta = (time.perf_counter() - t0) / nacc
+    step = tp + nu * ta
+    return {"value": 1.0 / step, "unit": "MH steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nprop} proposals and {nacc} accepts of the rocksalt workload on one core "
+                      f"(expansions not initialised; lattice moments formed in {t_setup:.1f} s), "
+                      f"t_prop={tp*1e3:.3f} ms, t_acc={ta*1e3:.3f} ms, combined at nu={nu:.3f}"}
+
+
+def run_batched(seed=4, steps=10000, nchains=256):
+    import workloads as W
+    from paper_2006_16622_amd import Chain, run_chains
+    import torch
+    chains, wls = [], []
+    t0 = time.perf_counter()
+    for c in range(nchains):
+        wl = W.batched_chain(c, nchains, steps=steps)
+        wls.append(wl)
+        chains.append(Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    # warmup a few steps (kernel load), then the timed launch
+    run_chains(chains, 20, seed, 1.0, [w.max_step for w in wls], t0=0, mode=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = run_chains(chains, steps, seed, 1.0, [w.max_step for w in wls], t0=20, mode=1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = chains[0].last_timing()[0] * 1e-3
+    acc = sum(s["accepted"] for s in st)
+    return {"value": nchains * steps / dt, "unit": "MH steps/s", "chains": nchains, "steps_per_chain": steps,
+            "kernel_s": kern, "wall_s": dt, "nu": acc / (nchains * steps), "setup_s": t_setup,
+            "n_range": [min(w.n for w in wls), max(w.n for w in wls)],
+            "depths": {str(d): sum(1 for w in wls if w.depth == d) for d in sorted({w.depth for w in wls})},
+            "status": [s["status"] for s in st if s["status"] != 0][:4]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=10000)
+    ap.add_argument("--mode", type=int, default=0, help="0 auto, 1 one workgroup, 2 whole GPU")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                          "launches": 3}))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this method's single chain does not shard, and the "
+              "batched chains are independent (see the scaling paragraph of the design notes); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2006_16622_amd import Chain, run_chains
+    from paper_2006_16622_amd import build as B
+    if not os.path.exists(B.LIB):
+        B.build()
+    wl = W.rocksalt()
+    log(f"[bench] workload {wl.name}: setup")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    m2l_ms = ch.last_timing()[1]
+    log(f"[bench] setup {t_setup*1e3:.1f} ms (M2L {m2l_ms:.2f} ms); warmup {args.warmup}")
+    run_chains([ch], args.warmup, wl.seed, wl.beta, wl.max_step, t0=0, mode=args.mode)
+    torch.cuda.synchronize()
+    pos_before = ch.positions()
+    log(f"[bench] timed {args.steps} steps")
+    t0 = time.perf_counter()
+    st, tr = run_chains([ch], args.steps, wl.seed, wl.beta, wl.max_step, t0=args.warmup, mode=args.mode,
+                        traces=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_s = ch.last_timing()[0] * 1e-3
+    s0 = st[0]
+    value = args.steps / dt
+    log(f"[bench] {value:.1f} steps/s (kernel {kern_s:.3f} s, wall {dt:.3f} s), accepted {s0['accepted']}")
+    prop_b, acc_b, nu, mean_t = algorithmic_bytes(wl, pos_before, tr["idx"][0], tr["newpos"][0], tr["acc"][0])
+    total_bytes = args.steps * prop_b + s0["accepted"] * acc_b
+    achieved = total_bytes / kern_s / 1e9
+    out = {
+        "metric": "MH steps/s at N=1e5 (1 chain) + aggregate over 256 chains; dE err vs Ewald",
+        "value": value,
+        "unit": "MH steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": wl.n, "depth": wl.depth, "p": wl.p, "beta": wl.beta,
+                   "max_step": wl.max_step, "chains": 1, "setup_ms": t_setup * 1e3, "setup_m2l_ms": m2l_ms,
+                   "acceptance": s0["accepted"] / args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_run_single", "kernel_s": kern_s,
+                     "bytes_per_proposal": prop_b, "bytes_per_accept": acc_b,
+                     "targets_per_accept": mean_t},
+    }
+    if not args.no_batched:
+        log("[bench] batched 256 chains")
+        out["batched"] = run_batched(steps=args.batched_steps)
+        log(f"[bench] batched {out['batched']['value']:.1f} steps/s")
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(wl, out["config"]["acceptance"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

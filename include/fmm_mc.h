@@ -112,6 +112,10 @@ typedef struct {
   double energy;    /* running total energy after the run */
   int32_t status;   /* FMM_MC_OK or an error code raised on the device */
   int32_t pad;
+  /* device time of the chain's proposing workgroup, microseconds (100 MHz
+   * realtime counter): proposals, its own share of accepted-move updates,
+   * and waiting for the other workgroups' shares (whole-GPU mode only) */
+  double t_propose_us, t_accept_us, t_wait_us;
 } fmm_mc_stats;
 
 /* Run `steps` Metropolis-Hastings steps on each chain, on the device. Step t

@@ -82,6 +82,7 @@ def _load():
         "orc_destroy": (None, [vp]),
         "orc_setup_fmm": (None, [vp, ctypes.c_int]),
         "orc_setup_direct": (None, [vp]),
+        "orc_setup_none": (None, [vp]),
         "orc_propose": (ctypes.c_double, [vp, ctypes.c_int, _dp]),
         "orc_accept": (None, [vp, ctypes.c_int, _dp]),
         "orc_energy": (ctypes.c_double, [vp]),
@@ -247,7 +248,9 @@ class Multilevel:
 
     ``setup`` is ``"fmm"`` (P2M, M2M, M2L; the initialisation the GPU path
     uses), ``"lazy"`` (the same, with each cell's M2L deferred to its first
-    use: for sampled checks at full size) or ``"direct"`` (Alg. L.3).
+    use: for sampled checks at full size), ``"direct"`` (Alg. L.3) or
+    ``"none"`` (zero expansions, lattice moments only: timing of the
+    per-step cost, never a reference value).
     """
 
     def __init__(self, pos, q, box: float, depth: int, p: int, setup: str = "fmm"):
@@ -266,6 +269,8 @@ class Multilevel:
             lib.orc_setup_fmm(self._h, 1)
         elif setup == "direct":
             lib.orc_setup_direct(self._h)
+        elif setup == "none":  # zero expansions: for timing the per-step cost only
+            lib.orc_setup_none(self._h)
         else:
             raise ValueError(setup)
 

@@ -740,6 +740,22 @@ void orc_setup_fmm(orc_t *st, int lazy) {
   }
 }
 
+/* No initialisation of the expansions: every L^Delta is zero, only the
+ * lattice moments are formed. The per-step cost of propose/accept does not
+ * depend on the coefficient values, so this state serves to time the
+ * oracle's steps on sizes whose initialisation would take too long on one
+ * core; it is never compared against. */
+void orc_setup_none(orc_t *st) {
+  st->lazy = 0;
+  st->nlog = 0;
+  init_lattice(st);
+  for (int l = 2; l <= st->L; ++l) {
+    size_t nc = (size_t)nside(l) * nside(l) * nside(l);
+    memset(st->Ld[l], 0, sizeof(cplx) * nc * st->C);
+    memset(st->ready[l], 1, nc);
+  }
+}
+
 /* Initialisation by direct P2L, Alg. L.3 (the paper's own setup): on every
  * level, every charge is added to the local expansion of every cell in the
  * interaction list of its cell (images included, Sec. 3.4). */

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfmm_mc.so")
+LIB_PATH = os.environ.get("FMM_MC_LIB", os.path.join(HERE, "libfmm_mc.so"))
 
 FMM_MC_MIXED = 0x1
 _ERRORS = {0: "ok", -1: "EINVAL", -2: "ERANGE", -3: "ENONNEUTRAL", -4: "ESINGULAR", -5: "ENOMEM",
@@ -36,7 +36,9 @@ class RunOpts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64),
                 ("singular", ctypes.c_int64), ("dE_sum", ctypes.c_double),
-                ("energy", ctypes.c_double), ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("energy", ctypes.c_double), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("t_propose_us", ctypes.c_double), ("t_accept_us", ctypes.c_double),
+                ("t_wait_us", ctypes.c_double)]
 
 
 _lib = None
@@ -232,7 +234,8 @@ def run_chains(chains, steps: int, seed: int, beta: float, max_step, t0: int = 0
     rc = lib.fmm_mc_run(hs, nc, int(steps), int(seed), ctypes.byref(opts), stats)
     _check(rc, "fmm_mc_run")
     out = [dict(proposed=s.proposed, accepted=s.accepted, singular=s.singular, dE_sum=s.dE_sum,
-                energy=s.energy, status=s.status) for s in stats]
+                energy=s.energy, status=s.status, t_propose_us=s.t_propose_us,
+                t_accept_us=s.t_accept_us, t_wait_us=s.t_wait_us) for s in stats]
     if traces:
         torch.cuda.synchronize(chains[0].device)
         tr = {k: v.cpu().numpy() for k, v in tr.items()}

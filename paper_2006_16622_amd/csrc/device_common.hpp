@@ -12,10 +12,39 @@ constexpr int NT = 256;       // threads per workgroup of every kernel
 constexpr int MAXL = 8;       // levels (depth 7)
 constexpr int NEAR = 27;      // leaf cells of a near region (Alg. 1)
 
+// largest degree of the unrolled harmonic recurrence for a group size
+template <int GS>
+struct PmaxOf {
+  static constexpr int v = GS == 16 ? 15 : 24;
+};
+
+// LDS layout shared by the propose and accept phases of one workgroup
+template <int GS>
+struct Lds {
+  static constexpr int NG = NT / GS;
+  double *rec;    // 3 Cs: staged recurrence constants
+  double *gbuf;   // NG Cs: one buffer per group
+  double *latO, *latN, *dk;  // Cs each
+  double *red;    // NT
+  double *vals;   // 32
+  int *ints;      // 384
+  __device__ Lds(double *base, int Cs) {
+    rec = base;
+    gbuf = rec + 3 * Cs;
+    latO = gbuf + (size_t)NG * Cs;
+    latN = latO + Cs;
+    dk = latN + Cs;
+    red = dk + Cs;
+    vals = red + NT;
+    ints = (int *)(vals + 32);
+  }
+  static size_t bytes(int Cs) { return sizeof(double) * ((size_t)(NG + 6) * Cs + NT + 32) + 4 * 384; }
+};
+
 // Constant tables shared by every chain of one degree p on one device.
 struct Tabs {
   int p, C, Cs;                 // degree, coefficients, padded stride
-  const double *rec;            // [3*Cs]: A_slot, B_slot (recurrence), diag[m]
+  const double *rec;            // [3*Cs]: A_slot, B_slot (recurrence), c_m (diagonal)
   const double *wl2p;           // [Cs] weights of the real-layout L2P: 1, 2 (Re), -2 (Im)
   const double *wdot;           // [Cs] weights of the bilinear form E.H: 1, 2, 2
   const double *sgnc;           // [Cs] +1 for m >= 0 slots, -1 for m < 0 (conjugation)
@@ -24,9 +53,9 @@ struct Tabs {
   const double *m2l;            // [316][C in][Cs out]
   const float *m2l32;           // same in FP32 (mixed precision)
   const double *m2m;            // [8][C in][Cs out]
-  const int *lat_row;           // CSR of the lattice operator, rows = output slots
-  const int *lat_col;
-  const double *lat_val;
+  int lat_w;                    // ELL width of the lattice operator
+  const int *lat_col;           // [lat_w][Cs] column of the w-th nonzero of row (output slot)
+  const double *lat_val;        // [lat_w][Cs] its value (0 in padding)
   double self_const;            // 6 + 8/sqrt3 + 12/sqrt2
 };
 
@@ -124,62 +153,78 @@ __device__ __forceinline__ void mh_draw(uint64_t seed, uint64_t chain, uint64_t 
 // ------------------------------------------------------------------ harmonics
 // One group of GS lanes evaluates, for one point x (already divided by the
 // cell size), the table of T_n^m(x) = |x|^n Y_n^m(x^), n <= p: lane m runs
-// the recurrence down column m (diagonal T_m^m by repeated multiplication
-// with (x + i y), then the three-term recurrence in n). The result goes to
-// the real-layout buffer buf (C doubles) as
-//   kind 0 (regular):         buf[n,m] = c Re T,         buf[n,-m] = c Im T
-//   kind 1 (conj. regular):   buf[n,m] = c Re T,         buf[n,-m] = -c Im T
-//   kind 2 (conj. irregular): buf[n,m] = c Re T / r^2n+1, buf[n,-m] = -c Im T / r^2n+1
-// (kind 1 is the P2M term q |s|^n Y_n^{-m}, kind 2 the P2L term
-// q |s|^-(n+1) Y_n^{-m} of Alg. L.2). With acc the values are added.
-template <int GS>
-__device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, double x, double y,
-                                                double z, int kind, double c, bool acc,
-                                                double *buf) {
-  const int p = tb.p;
-  const double *A = tb.rec, *Bc = tb.rec + tb.Cs, *dg = tb.rec + 2 * tb.Cs;
+// the recurrence down column m (diagonal T_m^m = c_m (x + i y)^m, then the
+// three-term recurrence in n). The result goes to the real-layout buffer
+// buf (C doubles) as
+//   KIND 0 (regular):         buf[n,m] = c Re T,         buf[n,-m] = c Im T
+//   KIND 1 (conj. regular):   buf[n,m] = c Re T,         buf[n,-m] = -c Im T
+//   KIND 2 (conj. irregular): buf[n,m] = c Re T / r^2n+1, buf[n,-m] = -c Im T / r^2n+1
+// (KIND 1 is the P2M term q |s|^n Y_n^{-m}, KIND 2 the P2L term
+// q |s|^-(n+1) Y_n^{-m} of Alg. L.2). With ACC the values are added.
+// The loops are unrolled to PMAX so that the recurrence constants of the
+// column are all loaded before the dependent arithmetic starts.
+// rec layout: [0, Cs) A(n,m), [Cs, 2Cs) B(n,m) at slot(n,m); [2Cs, 2Cs+p] c_m.
+template <int GS, int PMAX, int KIND, bool ACC>
+__device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const double *rec, double x,
+                                                double y, double z, double c, double *buf) {
+  const int p = tb.p, Cs = tb.Cs;
   for (int m = lane; m <= p; m += GS) {
-    double r2 = x * x + y * y + z * z;
-    double tr = 1.0, ti = 0.0;
-    double inv_r2 = 0.0, s = 1.0;
-    if (kind == 2) {
+    double Ar[PMAX + 1], Br[PMAX + 1];
+#pragma unroll
+    for (int j = 1; j <= PMAX; ++j) {
+      int n = m + j;
+      int sl = n <= p ? n * n + n + m : 0;
+      Ar[j] = rec[sl];
+      Br[j] = rec[Cs + sl];
+    }
+    const double cm = rec[2 * Cs + m];
+    const double r2 = x * x + y * y + z * z;
+    double tr = 1.0, ti = 0.0, inv_r2 = 0.0, s = 1.0;
+    if (KIND == 2) {
       inv_r2 = 1.0 / r2;
       s = sqrt(inv_r2);
     }
-    for (int i = 1; i <= m; ++i) {
-      double d = dg[i];
-      double nr = (tr * x - ti * y) * d;
-      double ni = (tr * y + ti * x) * d;
-      tr = nr;
-      ti = ni;
-      if (kind == 2) s *= inv_r2;
-    }
-    double pr = 0.0, pi = 0.0;  // T_{n-2}
-    double im_sign = (kind == 0) ? 1.0 : -1.0;
-    for (int n = m; n <= p; ++n) {
-      if (n > m) {
-        int sl = cslot(n, m);
-        double a = A[sl] * z, b = Bc[sl] * r2;
-        double nr = a * tr - b * pr;
-        double ni = a * ti - b * pi;
-        pr = tr;
-        pi = ti;
+#pragma unroll
+    for (int i = 1; i <= PMAX; ++i) {
+      if (i <= m) {
+        double nr = tr * x - ti * y;
+        double ni = tr * y + ti * x;
         tr = nr;
         ti = ni;
-        if (kind == 2) s *= inv_r2;
+        if (KIND == 2) s *= inv_r2;
       }
-      double f = c * s;
-      int sp = cslot(n, m);
-      if (acc)
-        buf[sp] += f * tr;
-      else
-        buf[sp] = f * tr;
-      if (m > 0) {
-        int sn = cslot(n, -m);
-        if (acc)
-          buf[sn] += im_sign * f * ti;
+    }
+    tr *= cm;
+    ti *= cm;
+    double pr = 0.0, pi = 0.0;  // T_{n-2}
+    const double im_sign = (KIND == 0) ? 1.0 : -1.0;
+#pragma unroll
+    for (int j = 0; j <= PMAX; ++j) {
+      const int n = m + j;
+      if (n <= p) {
+        if (j > 0) {
+          double a = Ar[j] * z, b = Br[j] * r2;
+          double nr = a * tr - b * pr;
+          double ni = a * ti - b * pi;
+          pr = tr;
+          pi = ti;
+          tr = nr;
+          ti = ni;
+          if (KIND == 2) s *= inv_r2;
+        }
+        const double f = c * s;
+        const int sp = n * n + n + m;
+        if (ACC)
+          buf[sp] += f * tr;
         else
-          buf[sn] = im_sign * f * ti;
+          buf[sp] = f * tr;
+        if (m > 0) {
+          const int sn = n * n + n - m;
+          if (ACC)
+            buf[sn] += im_sign * f * ti;
+          else
+            buf[sn] = im_sign * f * ti;
+        }
       }
     }
   }
@@ -191,6 +236,27 @@ __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
   for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GS);
   return v;
+}
+
+// deterministic workgroup sum of four values at once: shuffle tree inside
+// each wavefront, then the NT/64 wave totals in order; red: 16 doubles of LDS
+__device__ __forceinline__ void wg_sum4(double v[4], double *red) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[4 * wv + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[4 * w + k];
+    v[k] = s;
+  }
+  __syncthreads();
 }
 
 // deterministic workgroup sum (fixed tree); red: NT doubles of LDS
@@ -205,6 +271,25 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
   double r = red[0];
   __syncthreads();
   return r;
+}
+
+// y[s] = sum_k R[s][k] x[k] over the ELL layout of the lattice operator for
+// the output slots s = t, t + NT, ... of the calling thread; returns nothing,
+// the caller consumes y(s) through the functor
+template <typename F>
+__device__ __forceinline__ void lattice_rows(const Tabs &tb, const double *x, F &&use) {
+  for (int s = threadIdx.x; s < tb.C; s += NT) {
+    double v0 = 0.0, v1 = 0.0;
+    int w = 0;
+    for (; w + 1 < tb.lat_w; w += 2) {
+      double a0 = tb.lat_val[(size_t)w * tb.Cs + s], a1 = tb.lat_val[(size_t)(w + 1) * tb.Cs + s];
+      int c0 = tb.lat_col[(size_t)w * tb.Cs + s], c1 = tb.lat_col[(size_t)(w + 1) * tb.Cs + s];
+      v0 += a0 * x[c0];
+      v1 += a1 * x[c1];
+    }
+    if (w < tb.lat_w) v0 += tb.lat_val[(size_t)w * tb.Cs + s] * x[tb.lat_col[(size_t)w * tb.Cs + s]];
+    use(s, v0 + v1);
+  }
 }
 
 }  // namespace fmmdev

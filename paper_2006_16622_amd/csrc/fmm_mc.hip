@@ -72,7 +72,7 @@ int build_tables(int p, DevTables **out) {
   tb.C = C;
   tb.Cs = Cs;
   // recurrence constants: A(n,m) = (2n-1)/sqrt(n^2-m^2), B(n,m) =
-  // sqrt(((n-1)^2-m^2)/(n^2-m^2)) at slot(n,m); diag(m) = sqrt((2m-1)/(2m))
+  // sqrt(((n-1)^2-m^2)/(n^2-m^2)) at slot(n,m)
   std::vector<double> rec(3 * Cs, 0.0), wl2p(Cs, 0.0), wdot(Cs, 0.0), sgnc(Cs, 0.0);
   for (int n = 0; n <= p; ++n)
     for (int m = 0; m < n; ++m) {
@@ -80,7 +80,9 @@ int build_tables(int p, DevTables **out) {
       rec[s] = (2.0 * n - 1.0) / std::sqrt(double(n * n - m * m));
       rec[Cs + s] = std::sqrt(double((n - 1) * (n - 1) - m * m) / double(n * n - m * m));
     }
-  for (int m = 1; m <= p; ++m) rec[2 * Cs + m] = std::sqrt((2.0 * m - 1.0) / (2.0 * m));
+  // c_m = prod_{i<=m} sqrt((2i-1)/(2i)): T_m^m = c_m (x + i y)^m
+  rec[2 * Cs] = 1.0;
+  for (int m = 1; m <= p; ++m) rec[2 * Cs + m] = rec[2 * Cs + m - 1] * std::sqrt((2.0 * m - 1.0) / (2.0 * m));
   for (int n = 0; n <= p; ++n)
     for (int m = -n; m <= n; ++m) {
       int s = fmmhost::slot(n, m);
@@ -110,18 +112,27 @@ int build_tables(int p, DevTables **out) {
   }
   std::vector<double> lat((size_t)C * C);
   fmmhost::lattice_operator(p, lat.data());
-  std::vector<int> row(C + 1, 0), col;
-  std::vector<double> val;
+  // ELL layout (column-major by row) of the sparse lattice operator
+  int W = 1;
   for (int j = 0; j < C; ++j) {
+    int nz = 0;
+    for (int s = 0; s < C; ++s) nz += lat[(size_t)j * C + s] != 0.0;
+    W = std::max(W, nz);
+  }
+  std::vector<int> ecol((size_t)W * Cs, 0);
+  std::vector<double> eval((size_t)W * Cs, 0.0);
+  for (int j = 0; j < C; ++j) {
+    int w = 0;
     for (int s = 0; s < C; ++s) {
       double v = lat[(size_t)j * C + s];
       if (v != 0.0) {
-        col.push_back(s);
-        val.push_back(v);
+        ecol[(size_t)w * Cs + j] = s;
+        eval[(size_t)w * Cs + j] = v;
+        ++w;
       }
     }
-    row[j + 1] = (int)col.size();
   }
+  tb.lat_w = W;
   int rc = 0;
   rc |= upload(dt, rec, &tb.rec);
   rc |= upload(dt, wl2p, &tb.wl2p);
@@ -132,9 +143,8 @@ int build_tables(int p, DevTables **out) {
   rc |= upload(dt, m2l, &tb.m2l);
   rc |= upload(dt, m2l32, &tb.m2l32);
   rc |= upload(dt, m2m, &tb.m2m);
-  rc |= upload(dt, row, &tb.lat_row);
-  rc |= upload(dt, col, &tb.lat_col);
-  rc |= upload(dt, val, &tb.lat_val);
+  rc |= upload(dt, ecol, &tb.lat_col);
+  rc |= upload(dt, eval, &tb.lat_val);
   tb.self_const = 6.0 + 8.0 / std::sqrt(3.0) + 12.0 / std::sqrt(2.0);
   if (rc) {
     for (void *a : dt->allocs) (void)hipFree(a);
@@ -228,7 +238,7 @@ struct fmm_mc_ctx {
 namespace {
 
 size_t smem_bytes(int GS, int Cs) {
-  return GS == 16 ? Smem<16>::bytes(Cs) : Smem<32>::bytes(Cs);
+  return GS == 16 ? Lds<16>::bytes(Cs) : Lds<32>::bytes(Cs);
 }
 
 int grid_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
@@ -583,6 +593,7 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   rp.tr_leaf = tr_leaf;
   rp.stats = d_stats;
   bool single = (n_chains == 1 && mode != 1);
+  if (single) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 64);
   HIPCHK(hipEventRecord(h0->ev0, st));
   if (single) {
     const int NG = NT / GS;
@@ -595,7 +606,6 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
       HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_run_single<32>, NT, shm));
     int cap = std::max(1, ncu * std::max(per, 1));
     G = std::max(1, std::min(G, std::min(cap, ncu)));
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 64);
     Chain chv = h0->ch;
     void *args[] = {&chv, (void *)&tb, &rp};
     hipError_t e;
@@ -637,6 +647,9 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
       stats[c].dE_sum = hs[8 * c + 3];
       stats[c].energy = U[0];
       stats[c].status = (int32_t)hs[8 * c + 4];
+      stats[c].t_propose_us = hs[8 * c + 5];
+      stats[c].t_accept_us = hs[8 * c + 6];
+      stats[c].t_wait_us = hs[8 * c + 7];
     }
     if ((int)hs[8 * c + 4] != 0) rc = (int)hs[8 * c + 4];
   }

@@ -9,7 +9,7 @@
 
 namespace fmmdev {
 
-// A proposed or accepted move, known to every thread of a workgroup.
+// A proposed or accepted move, known to every thread of a workgroup (LDS).
 struct Move {
   int idx;
   double q;
@@ -32,13 +32,11 @@ __device__ __forceinline__ int lin3(int n, int x, int y, int z) { return x + n *
 __device__ __forceinline__ int imod(int i, int n) { return ((i % n) + n) % n; }
 __device__ __forceinline__ int ifloordiv(int i, int n) { return (i - imod(i, n)) / n; }
 
-// LDS layout shared by the propose and accept phases
+// copy the recurrence constants into LDS (all threads; caller syncs)
 template <int GS>
-struct Smem {
-  static constexpr int NG = NT / GS;
-  // group buffers NG * Cs, lattice buffers 2 * Cs, dk Cs, then scalars
-  static size_t bytes(int Cs) { return sizeof(double) * ((size_t)(NG + 3) * Cs + NT + 64) + 1024; }
-};
+__device__ __forceinline__ void stage_rec(const Tabs &tb, Lds<GS> &sm) {
+  for (int i = threadIdx.x; i < 3 * tb.Cs; i += NT) sm.rec[i] = tb.rec[i];
+}
 
 struct ProposeOut {
   double dE;
@@ -55,18 +53,11 @@ struct ProposeOut {
 // The new-side direct sum leaves out every image of the moving charge in
 // the near region together with the matching self term (they cancel).
 template <int GS>
-__device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, double *lds) {
-  constexpr int NG = NT / GS;
+__device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS> &sm) {
+  constexpr int NG = NT / GS, PM = PmaxOf<GS>::v;
   const int Cs = tb.Cs, C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
-  double *gbuf = lds;                        // NG * Cs
-  double *latO = lds + (size_t)NG * Cs;      // Cs
-  double *latN = latO + Cs;                  // Cs
-  double *dk = latN + Cs;                    // Cs
-  double *red = dk + Cs;                     // NT
-  double *vals = red + NT;                   // 32 point values
-  int *nbr = (int *)(vals + 32);             // 54 cells, 54 shifts-packed, 55 prefix, mask
-  int *ncell = nbr, *nshift = nbr + 54, *npre = nbr + 108, *nmask = nbr + 164;
+  int *ncell = sm.ints, *nshift = sm.ints + 54, *npre = sm.ints + 108, *nmask = sm.ints + 164;
 
   const double a = ch.a, q = mv.q;
   const int L = ch.L, d = ch.d;
@@ -83,12 +74,13 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     int w = (ifloordiv(b[0], n) + 1) + 3 * (ifloordiv(b[1], n) + 1) + 9 * (ifloordiv(b[2], n) + 1);
     ncell[t] = s;
     nshift[t] = w;
+    int cnt = ch.bin_cnt[s];
+    npre[t + 1] = cnt;  // counts, turned into a prefix sum below
   }
   if (t == 0) nmask[0] = 0;
   __syncthreads();
-  if (t < 64) {  // exclusive prefix sum of the 54 bin counts (wave 0)
-    int cnt = t < 54 ? ch.bin_cnt[ncell[t]] : 0;
-    int v = cnt;
+  if (t < 64) {  // inclusive scan of the 54 counts in wave 0
+    int v = t < 54 ? npre[t + 1] : 0;
     for (int o = 1; o < 64; o <<= 1) {
       int u = __shfl_up(v, o, 64);
       if (t >= o) v += u;
@@ -104,18 +96,15 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
       double *buf;
       double x[3], hh;
       const double *src;
-      int side;
       if (pt < 2) {  // lattice: expansion about the box centre, scaled by a
-        side = pt;
-        buf = side ? latN : latO;
-        const double *r = side ? mv.rn : mv.r;
+        buf = pt ? sm.latN : sm.latO;
+        const double *r = pt ? mv.rn : mv.r;
         hh = a;
         for (int k = 0; k < 3; ++k) x[k] = (r[k] - 0.5 * a) / a;
         src = ch.H;
       } else {
-        int l = 2 + (pt - 2) / 2;
-        side = (pt - 2) % 2;
-        buf = gbuf + (size_t)g * Cs;
+        int l = 2 + (pt - 2) / 2, side = (pt - 2) % 2;
+        buf = sm.gbuf + (size_t)g * Cs;
         int n = 1 << (l - 1);
         hh = a / n;
         const int *c = side ? mv.c1[l] : mv.c0[l];
@@ -123,13 +112,24 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
         for (int k = 0; k < 3; ++k) x[k] = (r[k] - (c[k] + 0.5) * hh) / hh;
         src = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
       }
-      group_harmonics<GS>(lane, tb, x[0], x[1], x[2], 0, 1.0, false, buf);
+      // the expansion coefficients are loaded while the harmonics are formed
+      double lv[(PmaxOf<GS>::v + 1) * (PmaxOf<GS>::v + 1) / GS + 1];
+#pragma unroll
+      for (int j = 0; j < (PM + 1) * (PM + 1) / GS + 1; ++j) {
+        int s = lane + j * GS;
+        lv[j] = s < C ? src[s] * tb.wl2p[s] : 0.0;
+      }
+      group_harmonics<GS, PM, 0, false>(lane, tb, sm.rec, x[0], x[1], x[2], 1.0, buf);
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       double acc = 0.0;
-      for (int s = lane; s < C; s += GS) acc += tb.wl2p[s] * src[s] * buf[s];
+#pragma unroll
+      for (int j = 0; j < (PM + 1) * (PM + 1) / GS + 1; ++j) {
+        int s = lane + j * GS;
+        if (s < C) acc += lv[j] * buf[s];
+      }
       acc = group_sum<GS>(acc);
-      if (lane == 0) vals[pt] = acc / hh;
+      if (lane == 0) sm.vals[pt] = acc / hh;
     }
     __syncthreads();
   }
@@ -137,9 +137,9 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
   // direct near field
   double dold = 0.0, dnew = 0.0;
   int singular = 0;
-  int total = npre[54];
+  const int total = npre[54];
   for (int i = t; i < total; i += NT) {
-    int lo = 0, hi = 54;  // find entry e with npre[e] <= i < npre[e+1]
+    int lo = 0, hi = 54;  // entry e with npre[e] <= i < npre[e+1]
     while (hi - lo > 1) {
       int mid = (lo + hi) >> 1;
       if (npre[mid] <= i) lo = mid; else hi = mid;
@@ -152,7 +152,7 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     const double *x = side ? mv.rn : mv.r;
     if (id == mv.idx) {
       if (side) atomicOr(&nmask[0], 1 << w);
-      if (side || w == 13) continue;  // w == 13: no shift
+      if (side || w == 13) continue;  // w == 13: no image shift
     }
     double dx = x[0] - (pj.x + sx), dy = x[1] - (pj.y + sy), dz = x[2] - (pj.z + sz);
     double r2 = dx * dx + dy * dy + dz * dz;
@@ -160,6 +160,8 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     double v = pj.w / sqrt(r2);
     if (side) dnew += v; else dold += v;
   }
+  // far lattice quadratic term: dk = q (conj T(r') - conj T(r)), 1/2 dk.R(dk)
+  for (int s = t; s < C; s += NT) sm.dk[s] = q * tb.sgnc[s] * (sm.latN[s] - sm.latO[s]);
   __syncthreads();
   // self-interaction with the old position's images (Sec. 3.4)
   double self = 0.0;
@@ -168,30 +170,21 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     double dx = mv.rn[0] - (mv.r[0] + sx), dy = mv.rn[1] - (mv.r[1] + sy), dz = mv.rn[2] - (mv.r[2] + sz);
     self = q * q / sqrt(dx * dx + dy * dy + dz * dz);
   }
-  // far lattice quadratic term: dk = q (conj T(r') - conj T(r)), 1/2 dk.R(dk)
-  for (int s = t; s < C; s += NT) dk[s] = q * tb.sgnc[s] * (latN[s] - latO[s]);
-  __syncthreads();
   double quad = 0.0;
-  for (int s = t; s < C; s += NT) {
-    double v = 0.0;
-    for (int k = tb.lat_row[s]; k < tb.lat_row[s + 1]; ++k) v += tb.lat_val[k] * dk[tb.lat_col[k]];
-    quad += tb.wdot[s] * dk[s] * v;
-  }
-  double s_dold = wg_sum(dold, red);
-  double s_dnew = wg_sum(dnew, red);
-  double s_self = wg_sum(self, red);
-  double s_quad = wg_sum(quad, red);
+  lattice_rows(tb, sm.dk, [&](int s, double v) { quad += tb.wdot[s] * sm.dk[s] * v; });
+  double part[4] = {dold, dnew, self, quad};
+  wg_sum4(part, sm.red);
   int sing = __syncthreads_or(singular);
 
   ProposeOut out;
   double dE = 0.0;
   for (int l = 2; l <= L; ++l) {
     int po = 2 + 2 * (l - 2);
-    dE += q * (vals[po + 1] - vals[po]);
+    dE += q * (sm.vals[po + 1] - sm.vals[po]);
   }
-  dE += q * (s_dnew - s_dold);
-  dE += -s_self + q * q / a * tb.self_const;
-  dE += q * (vals[1] - vals[0]) + 0.5 * s_quad / a;
+  dE += q * (part[1] - part[0]);
+  dE += -part[2] + q * q / a * tb.self_const;
+  dE += q * (sm.vals[1] - sm.vals[0]) + 0.5 * part[3] / a;
   double dr[3] = {mv.rn[0] - mv.r[0], mv.rn[1] - mv.r[1], mv.rn[2] - mv.r[2]};
   double Ddot = ch.dip[0] * dr[0] + ch.dip[1] * dr[1] + ch.dip[2] * dr[2];
   double dd = dr[0] * dr[0] + dr[1] * dr[1] + dr[2] * dr[2];
@@ -210,9 +203,6 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
 // list never holds two images of one cell): blocks of NG items, one item per
 // offset of IL(a_l) and IL(a'_l); a stored cell lying in both lists is
 // handled by the old-side item.
-template <int GS>
-__host__ __device__ constexpr int items_per_block() { return NT / GS; }
-
 __host__ __device__ inline int accept_blocks(int L, int NG) {
   int nb = 0;
   if (L >= 2) nb += 8;
@@ -238,12 +228,12 @@ __device__ __forceinline__ bool image_in_il(const int s[3], const int c[3], int 
 }
 
 template <int GS>
-__device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, int blk, double *lds) {
-  constexpr int NG = NT / GS;
+__device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS> &sm) {
+  constexpr int NG = NT / GS, PM = PmaxOf<GS>::v;
   const int Cs = tb.Cs, C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
-  double *acc = lds;                      // NG * Cs
-  int *lst = (int *)(lds + (size_t)(NG + 3) * Cs + NT + 32);  // candidate list
+  double *acc = sm.gbuf;  // NG * Cs
+  int *lst = sm.ints;     // candidate list
   const double a = ch.a, q = mv.q;
   const int L = ch.L;
 
@@ -295,7 +285,8 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
       const double *x = side ? mv.rn : mv.r;
       double v[3];
       for (int k = 0; k < 3; ++k) v[k] = (x[k] - ((s[k] + n * w[k]) + 0.5) * h) / h;
-      group_harmonics<GS>(lane, tb, v[0], v[1], v[2], 2, side ? q : -q, true, acc + (size_t)g * Cs);
+      group_harmonics<GS, PM, 2, true>(lane, tb, sm.rec, v[0], v[1], v[2], side ? q : -q,
+                                       acc + (size_t)g * Cs);
     }
     __syncthreads();
     double *dst = ch.Ld + ch.ld_off[l] + (size_t)s_lin * Cs;
@@ -308,7 +299,7 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
     return;
   }
   // ---- fine levels: item = (level, side, IL offset)
-  int b2 = blk - (L >= 3 ? 72 : 8);
+  int b2 = blk - 72;
   const int bpl = (378 + NG - 1) / NG;
   const int l = 4 + b2 / bpl;
   const int item = (b2 % bpl) * NG + g;
@@ -326,50 +317,56 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
     bool other = image_in_il(s, co, n, b_other);
     if (side == 1 && other) return;  // owned by the old-side item
     double *buf = acc + (size_t)g * Cs;
+    const double *dstc = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * Cs;
+    // the target's coefficients are loaded while the harmonics are formed
+    double old[(PmaxOf<GS>::v + 1) * (PmaxOf<GS>::v + 1) / GS + 1];
+#pragma unroll
+    for (int j = 0; j < (PM + 1) * (PM + 1) / GS + 1; ++j) {
+      int k = lane + j * GS;
+      old[j] = k < C ? dstc[k] : 0.0;
+    }
     const double *x = side ? mv.rn : mv.r;
     double v[3];
     for (int k = 0; k < 3; ++k) v[k] = (x[k] - (b[k] + 0.5) * h) / h;
-    group_harmonics<GS>(lane, tb, v[0], v[1], v[2], 2, side ? q : -q, false, buf);
+    group_harmonics<GS, PM, 2, false>(lane, tb, sm.rec, v[0], v[1], v[2], side ? q : -q, buf);
     if (side == 0 && other) {
       __builtin_amdgcn_wave_barrier();
       for (int k = 0; k < 3; ++k) v[k] = (mv.rn[k] - (b_other[k] + 0.5) * h) / h;
-      group_harmonics<GS>(lane, tb, v[0], v[1], v[2], 2, q, true, buf);
+      group_harmonics<GS, PM, 2, true>(lane, tb, sm.rec, v[0], v[1], v[2], q, buf);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     double *dst = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * Cs;
-    for (int k = lane; k < C; k += GS) dst[k] += buf[k];
+#pragma unroll
+    for (int j = 0; j < (PM + 1) * (PM + 1) / GS + 1; ++j) {
+      int k = lane + j * GS;
+      if (k < C) dst[k] = old[j] + buf[k];
+    }
   }
 }
 
 // Bookkeeping of an accepted move by one workgroup: K += dk, H += R(dk),
-// dipole, running energy, position and leaf bins (Sec. 3.4; Sec. 5.2's
-// indirection map). Returns nonzero on bin overflow.
+// dipole, running energy, position and leaf bins (Sec. 3.4; the particle
+// to cell map of Sec. 5.2). Returns nonzero on bin overflow.
 template <int GS>
-__device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &mv, double dE,
-                                  double *lds) {
-  constexpr int NG = NT / GS;
-  const int Cs = tb.Cs, C = tb.C;
+__device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &mv, double dE, Lds<GS> &sm) {
+  constexpr int PM = PmaxOf<GS>::v;
+  const int C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
-  double *latO = lds + (size_t)NG * Cs, *latN = latO + Cs, *dk = latN + Cs;
-  int *flag = (int *)(dk + Cs + NT + 32) + 200;
+  int *flag = sm.ints + 200;
   const double a = ch.a, q = mv.q;
   if (g < 2) {
     const double *r = g ? mv.rn : mv.r;
-    group_harmonics<GS>(lane, tb, (r[0] - 0.5 * a) / a, (r[1] - 0.5 * a) / a, (r[2] - 0.5 * a) / a, 1,
-                        1.0, false, g ? latN : latO);
+    group_harmonics<GS, PM, 1, false>(lane, tb, sm.rec, (r[0] - 0.5 * a) / a, (r[1] - 0.5 * a) / a,
+                                      (r[2] - 0.5 * a) / a, 1.0, g ? sm.latN : sm.latO);
   }
   __syncthreads();
   for (int s = t; s < C; s += NT) {
-    dk[s] = q * (latN[s] - latO[s]);
-    ch.K[s] += dk[s];
+    sm.dk[s] = q * (sm.latN[s] - sm.latO[s]);
+    ch.K[s] += sm.dk[s];
   }
   __syncthreads();
-  for (int s = t; s < C; s += NT) {
-    double v = 0.0;
-    for (int k = tb.lat_row[s]; k < tb.lat_row[s + 1]; ++k) v += tb.lat_val[k] * dk[tb.lat_col[k]];
-    ch.H[s] += v;
-  }
+  lattice_rows(tb, sm.dk, [&](int s, double v) { ch.H[s] += v; });
   if (t == 0) {
     int ovf = 0;
     for (int k = 0; k < 3; ++k) ch.dip[k] += q * (mv.rn[k] - mv.r[k]);

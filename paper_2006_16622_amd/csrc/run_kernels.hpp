@@ -73,11 +73,15 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
   __shared__ double s_dE;
   const int c = blockIdx.x, t = threadIdx.x;
   const Chain ch = chains[c];
+  Lds<GS> sm(lds, tb.Cs);
+  stage_rec(tb, sm);
   const double D = rp.max_step[c];
   const int nblk = accept_blocks(ch.L, NG);
   double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
+  uint64_t tick_prop = 0, tick_acc = 0;
   int status = 0;
   for (int64_t step = 0; step < rp.steps; ++step) {
+    uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
     if (t == 0) {
       int64_t idx;
       double rn_abs[3], u;
@@ -87,7 +91,9 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
     }
     __syncthreads();
     double u = s_dE;
-    ProposeOut po = propose_wg<GS>(ch, tb, mv, lds);
+    ProposeOut po = propose_wg<GS>(ch, tb, mv, sm);
+    uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
+    tick_prop += t_1 - t_0;
     if (t == 0) {
       int acc = !po.singular && (u < exp(-rp.beta * po.dE));
       s_acc = acc;
@@ -107,14 +113,15 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
     __syncthreads();
     if (s_acc) {
       for (int b = 0; b < nblk; ++b) {
-        accept_block<GS>(ch, tb, mv, b, lds);
+        accept_block<GS>(ch, tb, mv, b, sm);
         __syncthreads();
       }
-      int ovf = accept_bookkeeping<GS>(ch, tb, mv, po.dE, lds);
+      int ovf = accept_bookkeeping<GS>(ch, tb, mv, po.dE, sm);
       if (t == 0) {
         nacc += 1;
         dEsum += po.dE;
       }
+      tick_acc += __builtin_amdgcn_s_memrealtime() - t_1;
       if (ovf) {
         status = -7;
         break;
@@ -128,22 +135,27 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
     st[2] = nsing;
     st[3] = dEsum;
     st[4] = status;
+    st[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
+    st[6] = tick_acc * 0.01;
+    st[7] = 0.0;
   }
 }
 
 // ---------------------------------------------------------------- single chain
-__device__ __forceinline__ unsigned ld_acquire(unsigned *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Polling uses relaxed agent-scope loads (no cache invalidation per poll);
+// the caller issues one acquire fence after the awaited value is seen.
+__device__ __forceinline__ unsigned ld_relaxed(unsigned *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_release(unsigned *p, unsigned v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// bounded spin: returns false after `limit_ticks` of the 100 MHz clock
+// bounded spin: returns false after `limit` ticks of the 100 MHz clock
 __device__ __forceinline__ bool spin_until_ne(unsigned *p, unsigned old, unsigned &val, uint64_t limit) {
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   while (true) {
-    val = ld_acquire(p);
+    val = ld_relaxed(p);
     if (val != old) return true;
     if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
     __builtin_amdgcn_s_sleep(1);
@@ -152,7 +164,7 @@ __device__ __forceinline__ bool spin_until_ne(unsigned *p, unsigned old, unsigne
 __device__ __forceinline__ bool spin_until_ge(unsigned *p, unsigned target, uint64_t limit) {
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   while (true) {
-    unsigned v = ld_acquire(p);
+    unsigned v = ld_relaxed(p);
     if ((int)(v - target) >= 0) return true;
     if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
     __builtin_amdgcn_s_sleep(1);
@@ -169,6 +181,9 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
   __shared__ int s_flag, s_acc;
   __shared__ double s_u;
   const int t = threadIdx.x, w = blockIdx.x, G = gridDim.x;
+  Lds<GS> sm(lds, tb.Cs);
+  stage_rec(tb, sm);
+  __syncthreads();
   const int nblk = accept_blocks(ch.L, NG);
   unsigned *seq = ch.sync, *done = ch.sync + 1, *stop = ch.sync + 2, *err = ch.sync + 3;
   double *mb = ch.mbox;
@@ -177,7 +192,9 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
     double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
     int status = 0;
     unsigned myseq = 0, expect = 0;
+    uint64_t tick_prop = 0, tick_acc = 0, tick_wait = 0;
     for (int64_t step = 0; step < rp.steps; ++step) {
+      uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
       if (t == 0) {
         int64_t idx;
         double rn_abs[3], u;
@@ -186,7 +203,9 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
         s_u = u;
       }
       __syncthreads();
-      ProposeOut po = propose_wg<GS>(ch, tb, mv, lds);
+      ProposeOut po = propose_wg<GS>(ch, tb, mv, sm);
+      uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
+      tick_prop += t_1 - t_0;
       if (t == 0) {
         int acc = !po.singular && (s_u < exp(-rp.beta * po.dE));
         s_acc = acc;
@@ -218,14 +237,16 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
           if (t == 0) st_release(seq, ++myseq);
         }
         for (int b = 0; b < nblk; b += G) {
-          accept_block<GS>(ch, tb, mv, b, lds);
+          accept_block<GS>(ch, tb, mv, b, sm);
           __syncthreads();
         }
-        int ovf = accept_bookkeeping<GS>(ch, tb, mv, po.dE, lds);
+        int ovf = accept_bookkeeping<GS>(ch, tb, mv, po.dE, sm);
         if (t == 0) {
           nacc += 1;
           dEsum += po.dE;
         }
+        uint64_t t_2 = __builtin_amdgcn_s_memrealtime();
+        tick_acc += t_2 - t_1;
         if (G > 1) {
           expect += (unsigned)(G - 1);
           if (t == 0) s_flag = spin_until_ge(done, expect, SPIN_LIMIT) ? 0 : 1;
@@ -236,6 +257,7 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
             break;
           }
         }
+        tick_wait += __builtin_amdgcn_s_memrealtime() - t_2;
         if (ovf) {
           status = -7;
           break;
@@ -252,6 +274,9 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
       rp.stats[2] = nsing;
       rp.stats[3] = dEsum;
       rp.stats[4] = status;
+      rp.stats[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
+      rp.stats[6] = tick_acc * 0.01;
+      rp.stats[7] = tick_wait * 0.01;
     }
     return;
   }
@@ -270,7 +295,6 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     int f = s_flag;
-    if (t == 0) myseq = myseq;  // keep
     __syncthreads();
     if (f == 1) {
       if (t == 0) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -291,7 +315,7 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
     }
     __syncthreads();
     for (int b = w; b < nblk; b += G) {
-      accept_block<GS>(ch, tb, mv, b, lds);
+      accept_block<GS>(ch, tb, mv, b, sm);
       __syncthreads();
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -306,12 +330,14 @@ __global__ void __launch_bounds__(NT) k_propose_one(Chain ch, Tabs tb, int64_t i
                                                     double z) {
   extern __shared__ double lds[];
   __shared__ Move mv;
+  Lds<GS> sm(lds, tb.Cs);
+  stage_rec(tb, sm);
   if (threadIdx.x == 0) {
     double rn_abs[3] = {x, y, z};
     fill_move(ch, mv, idx, rn_abs);
   }
   __syncthreads();
-  ProposeOut po = propose_wg<GS>(ch, tb, mv, lds);
+  ProposeOut po = propose_wg<GS>(ch, tb, mv, sm);
   if (threadIdx.x == 0) {
     ch.scratch[0] = po.dE;
     ch.scratch[1] = po.singular;
@@ -323,12 +349,14 @@ __global__ void __launch_bounds__(NT) k_accept_blocks(Chain ch, Tabs tb, int64_t
                                                       double z) {
   extern __shared__ double lds[];
   __shared__ Move mv;
+  Lds<GS> sm(lds, tb.Cs);
+  stage_rec(tb, sm);
   if (threadIdx.x == 0) {
     double rn_abs[3] = {x, y, z};
     fill_move(ch, mv, idx, rn_abs);
   }
   __syncthreads();
-  accept_block<GS>(ch, tb, mv, blockIdx.x, lds);
+  accept_block<GS>(ch, tb, mv, blockIdx.x, sm);
 }
 
 template <int GS>
@@ -336,12 +364,14 @@ __global__ void __launch_bounds__(NT) k_accept_book(Chain ch, Tabs tb, int64_t i
                                                     double z, double dE) {
   extern __shared__ double lds[];
   __shared__ Move mv;
+  Lds<GS> sm(lds, tb.Cs);
+  stage_rec(tb, sm);
   if (threadIdx.x == 0) {
     double rn_abs[3] = {x, y, z};
     fill_move(ch, mv, idx, rn_abs);
   }
   __syncthreads();
-  int ovf = accept_bookkeeping<GS>(ch, tb, mv, dE, lds);
+  int ovf = accept_bookkeeping<GS>(ch, tb, mv, dE, sm);
   if (threadIdx.x == 0 && ovf) ch.status[0] = -7;
 }
 

@@ -81,8 +81,9 @@ __global__ void k_p2m_leaf(Chain ch, Tabs tb, int nleaf) {
   int cnt = ch.bin_cnt[c];
   for (int j = 0; j < cnt; ++j) {
     double4 pj = ch.bin_p[(size_t)c * ch.B + j];
-    group_harmonics<GS>(lane, tb, (pj.x - (cx + 0.5) * h) / h, (pj.y - (cy + 0.5) * h) / h,
-                        (pj.z - (cz + 0.5) * h) / h, 1, pj.w, true, buf);
+    group_harmonics<GS, PmaxOf<GS>::v, 1, true>(lane, tb, tb.rec, (pj.x - (cx + 0.5) * h) / h,
+                                                (pj.y - (cy + 0.5) * h) / h, (pj.z - (cz + 0.5) * h) / h,
+                                                pj.w, buf);
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -193,11 +194,7 @@ __global__ void k_lattice_init(Chain ch, Tabs tb) {
   const double *M1 = ch.Mp + ch.mp_off[1];
   for (int s = t; s < C; s += NT) ch.K[s] = M1[s];
   __syncthreads();
-  for (int s = t; s < C; s += NT) {
-    double v = 0.0;
-    for (int k = tb.lat_row[s]; k < tb.lat_row[s + 1]; ++k) v += tb.lat_val[k] * M1[tb.lat_col[k]];
-    ch.H[s] = v;
-  }
+  lattice_rows(tb, M1, [&](int s, double v) { ch.H[s] = v; });
   double d[3] = {0, 0, 0};
   for (int i = t; i < ch.N; i += NT) {
     d[0] += ch.pq[i] * ch.px[i];
@@ -231,8 +228,9 @@ __global__ void k_energy(Chain ch, Tabs tb) {
       double h = a / n;
       int c[3];
       for (int k = 0; k < 3; ++k) c[k] = cell_coord(r[k], a, n);
-      group_harmonics<GS>(lane, tb, (r[0] - (c[0] + 0.5) * h) / h, (r[1] - (c[1] + 0.5) * h) / h,
-                          (r[2] - (c[2] + 0.5) * h) / h, 0, 1.0, false, buf);
+      group_harmonics<GS, PmaxOf<GS>::v, 0, false>(lane, tb, tb.rec, (r[0] - (c[0] + 0.5) * h) / h,
+                                                   (r[1] - (c[1] + 0.5) * h) / h,
+                                                   (r[2] - (c[2] + 0.5) * h) / h, 1.0, buf);
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       const double *src = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
