@@ -18,29 +18,6 @@ struct PmaxOf {
   static constexpr int v = GS == 16 ? 15 : 24;
 };
 
-// LDS layout shared by the propose and accept phases of one workgroup
-template <int GS>
-struct Lds {
-  static constexpr int NG = NT / GS;
-  double *rec;    // 3 Cs: staged recurrence constants
-  double *gbuf;   // NG Cs: one buffer per group
-  double *latO, *latN, *dk;  // Cs each
-  double *red;    // NT
-  double *vals;   // 32
-  int *ints;      // 384
-  __device__ Lds(double *base, int Cs) {
-    rec = base;
-    gbuf = rec + 3 * Cs;
-    latO = gbuf + (size_t)NG * Cs;
-    latN = latO + Cs;
-    dk = latN + Cs;
-    red = dk + Cs;
-    vals = red + NT;
-    ints = (int *)(vals + 32);
-  }
-  static size_t bytes(int Cs) { return sizeof(double) * ((size_t)(NG + 6) * Cs + NT + 32) + 4 * 384; }
-};
-
 // Constant tables shared by every chain of one degree p on one device.
 struct Tabs {
   int p, C, Cs;                 // degree, coefficients, padded stride
@@ -54,6 +31,7 @@ struct Tabs {
   const float *m2l32;           // same in FP32 (mixed precision)
   const double *m2m;            // [8][C in][Cs out]
   int lat_w;                    // ELL width of the lattice operator
+  int lat_lds;                  // nonzero: the run kernels keep it in LDS
   const int *lat_col;           // [lat_w][Cs] column of the w-th nonzero of row (output slot)
   const double *lat_val;        // [lat_w][Cs] its value (0 in padding)
   double self_const;            // 6 + 8/sqrt3 + 12/sqrt2
@@ -64,6 +42,7 @@ struct Chain {
   int N, d, L, B;               // charges, depth, levels (d+1), bin capacity
   int mixed;
   double a;                     // box side
+  double inv_h[MAXL + 2];       // n_l / a on level l (cells per unit length), one IEEE division
   double *px, *py, *pz, *pq;    // particles by id (wrapped positions)
   int *leaf_of, *slot_of;
   int *bin_cnt, *bin_id;        // [nleaf], [nleaf*B]
@@ -81,6 +60,50 @@ struct Chain {
   unsigned *sync;               // [4] sequence / done counters
   double *red;                  // partial sums of reductions
   double *stage;                // raw host positions (3N) then charges (N)
+};
+
+// LDS layout of one workgroup of the Monte Carlo kernels. Besides scratch
+// for the propose and accept phases it holds, for the whole launch, the
+// constant tables the step needs (recurrence constants, L2P and bilinear
+// weights, optionally the lattice operator) and the chain's small mutable
+// state (K, H = R(K), dipole, running energy), written back at the end.
+template <int GS>
+struct Lds {
+  static constexpr int NG = NT / GS;
+  double *rec;                 // 3 Cs: recurrence constants
+  double *wl2p, *wdot, *sgnc;  // Cs each
+  double *H, *K;               // Cs each: chain state
+  double *st;                  // 8: dipole[3], running energy, setup energy
+  double *lat_val;             // W Cs (when resident)
+  int *lat_col;                // W Cs (when resident)
+  double *gbuf;                // NG Cs: one buffer per group
+  double *latO, *latN, *dk;    // Cs each
+  double *red;                 // NT
+  double *vals;                // 32
+  double4 *stash;              // 2: records kept by the proposal for the bookkeeping
+  int *ints;                   // 384
+  __device__ Lds(double *base, int Cs, int ellw) {
+    rec = base;
+    wl2p = rec + 3 * Cs;
+    wdot = wl2p + Cs;
+    sgnc = wdot + Cs;
+    H = sgnc + Cs;
+    K = H + Cs;
+    st = K + Cs;
+    lat_val = st + 8;
+    gbuf = lat_val + (size_t)ellw * Cs;
+    latO = gbuf + (size_t)NG * Cs;
+    latN = latO + Cs;
+    dk = latN + Cs;
+    red = dk + Cs;
+    vals = red + NT;
+    stash = (double4 *)(vals + 32);
+    ints = (int *)(stash + 2);
+    lat_col = ints + 384;
+  }
+  static size_t bytes(int Cs, int ellw) {
+    return sizeof(double) * ((size_t)(NG + 12 + ellw) * Cs + 8 + NT + 32 + 8) + 4 * (384 + (size_t)ellw * Cs);
+  }
 };
 
 __device__ __forceinline__ int cslot(int n, int m) { return n * n + n + m; }
@@ -102,10 +125,10 @@ __device__ __forceinline__ double wrap_coord(double x, double a) {
   return w;
 }
 
-// floor(x * (n/a)) clamped to [0, n-1]; a point on a face goes to the upper cell
-__device__ __forceinline__ int cell_coord(double x, double a, int n) {
+// floor(x * (n/a)) clamped to [0, n-1]; a point on a face goes to the upper
+// cell. inv = n/a is formed once per level by one IEEE division.
+__device__ __forceinline__ int cell_coord(double x, double inv, int n) {
 #pragma clang fp contract(off)
-  double inv = (double)n / a;
   int i = (int)floor(x * inv);
   return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
 }
@@ -151,10 +174,11 @@ __device__ __forceinline__ void mh_draw(uint64_t seed, uint64_t chain, uint64_t 
 }
 
 // ------------------------------------------------------------------ harmonics
-// One group of GS lanes evaluates, for one point x (already divided by the
-// cell size), the table of T_n^m(x) = |x|^n Y_n^m(x^), n <= p: lane m runs
-// the recurrence down column m (diagonal T_m^m = c_m (x + i y)^m, then the
-// three-term recurrence in n). The result goes to the real-layout buffer
+// One group of GS lanes (GS > p) evaluates, for one point x (already divided
+// by the cell size), the table of T_n^m(x) = |x|^n Y_n^m(x^), n <= p: lane m
+// forms the diagonal T_m^m = c_m (x + i y)^m (the powers by a scan over the
+// lanes) and runs the three-term recurrence in n down column m. Every lane
+// of the group must call it. The result goes to the real-layout buffer
 // buf (C doubles) as
 //   KIND 0 (regular):         buf[n,m] = c Re T,         buf[n,-m] = c Im T
 //   KIND 1 (conj. regular):   buf[n,m] = c Re T,         buf[n,-m] = -c Im T
@@ -168,63 +192,66 @@ template <int GS, int PMAX, int KIND, bool ACC>
 __device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const double *rec, double x,
                                                 double y, double z, double c, double *buf) {
   const int p = tb.p, Cs = tb.Cs;
-  for (int m = lane; m <= p; m += GS) {
-    double Ar[PMAX + 1], Br[PMAX + 1];
+  const int m = lane;
+  const double r2 = x * x + y * y + z * z;
+  // (x + i y)^m and, for KIND 2, |x|^-(2m+1), by a multiplicative scan over the lanes
+  double wr = m == 0 ? 1.0 : x, wi = m == 0 ? 0.0 : y;
+  double inv_r2 = 0.0, s = 1.0;
+  if (KIND == 2) {
+    inv_r2 = 1.0 / r2;
+    s = m == 0 ? sqrt(inv_r2) : inv_r2;
+  }
 #pragma unroll
-    for (int j = 1; j <= PMAX; ++j) {
-      int n = m + j;
-      int sl = n <= p ? n * n + n + m : 0;
-      Ar[j] = rec[sl];
-      Br[j] = rec[Cs + sl];
+  for (int o = 1; o < GS; o <<= 1) {
+    double ur = __shfl_up(wr, o, GS), ui = __shfl_up(wi, o, GS);
+    double us = KIND == 2 ? __shfl_up(s, o, GS) : 1.0;
+    if (lane >= o) {
+      double nr = wr * ur - wi * ui;
+      double ni = wr * ui + wi * ur;
+      wr = nr;
+      wi = ni;
+      if (KIND == 2) s *= us;
     }
-    const double cm = rec[2 * Cs + m];
-    const double r2 = x * x + y * y + z * z;
-    double tr = 1.0, ti = 0.0, inv_r2 = 0.0, s = 1.0;
-    if (KIND == 2) {
-      inv_r2 = 1.0 / r2;
-      s = sqrt(inv_r2);
-    }
+  }
+  if (m > p) return;
+  double Ar[PMAX + 1], Br[PMAX + 1];
 #pragma unroll
-    for (int i = 1; i <= PMAX; ++i) {
-      if (i <= m) {
-        double nr = tr * x - ti * y;
-        double ni = tr * y + ti * x;
+  for (int j = 1; j <= PMAX; ++j) {
+    int n = m + j;
+    int sl = n <= p ? n * n + n + m : 0;
+    Ar[j] = rec[sl];
+    Br[j] = rec[Cs + sl];
+  }
+  const double cm = rec[2 * Cs + m];
+  double tr = wr * cm, ti = wi * cm;
+  double pr = 0.0, pi = 0.0;  // T_{n-2}
+  const double im_sign = (KIND == 0) ? 1.0 : -1.0;
+#pragma unroll
+  for (int j = 0; j <= PMAX; ++j) {
+    const int n = m + j;
+    if (n <= p) {
+      if (j > 0) {
+        double a = Ar[j] * z, b = Br[j] * r2;
+        double nr = a * tr - b * pr;
+        double ni = a * ti - b * pi;
+        pr = tr;
+        pi = ti;
         tr = nr;
         ti = ni;
         if (KIND == 2) s *= inv_r2;
       }
-    }
-    tr *= cm;
-    ti *= cm;
-    double pr = 0.0, pi = 0.0;  // T_{n-2}
-    const double im_sign = (KIND == 0) ? 1.0 : -1.0;
-#pragma unroll
-    for (int j = 0; j <= PMAX; ++j) {
-      const int n = m + j;
-      if (n <= p) {
-        if (j > 0) {
-          double a = Ar[j] * z, b = Br[j] * r2;
-          double nr = a * tr - b * pr;
-          double ni = a * ti - b * pi;
-          pr = tr;
-          pi = ti;
-          tr = nr;
-          ti = ni;
-          if (KIND == 2) s *= inv_r2;
-        }
-        const double f = c * s;
-        const int sp = n * n + n + m;
+      const double f = c * s;
+      const int sp = n * n + n + m;
+      if (ACC)
+        buf[sp] += f * tr;
+      else
+        buf[sp] = f * tr;
+      if (m > 0) {
+        const int sn = n * n + n - m;
         if (ACC)
-          buf[sp] += f * tr;
+          buf[sn] += im_sign * f * ti;
         else
-          buf[sp] = f * tr;
-        if (m > 0) {
-          const int sn = n * n + n - m;
-          if (ACC)
-            buf[sn] += im_sign * f * ti;
-          else
-            buf[sn] = im_sign * f * ti;
-        }
+          buf[sn] = im_sign * f * ti;
       }
     }
   }
@@ -274,20 +301,20 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
 }
 
 // y[s] = sum_k R[s][k] x[k] over the ELL layout of the lattice operator for
-// the output slots s = t, t + NT, ... of the calling thread; returns nothing,
-// the caller consumes y(s) through the functor
+// the output slots s = t, t + NT, ... of the calling thread, handed to `use`
 template <typename F>
-__device__ __forceinline__ void lattice_rows(const Tabs &tb, const double *x, F &&use) {
+__device__ __forceinline__ void lattice_rows(const Tabs &tb, const double *val, const int *col,
+                                             const double *x, F &&use) {
   for (int s = threadIdx.x; s < tb.C; s += NT) {
     double v0 = 0.0, v1 = 0.0;
     int w = 0;
     for (; w + 1 < tb.lat_w; w += 2) {
-      double a0 = tb.lat_val[(size_t)w * tb.Cs + s], a1 = tb.lat_val[(size_t)(w + 1) * tb.Cs + s];
-      int c0 = tb.lat_col[(size_t)w * tb.Cs + s], c1 = tb.lat_col[(size_t)(w + 1) * tb.Cs + s];
+      double a0 = val[(size_t)w * tb.Cs + s], a1 = val[(size_t)(w + 1) * tb.Cs + s];
+      int c0 = col[(size_t)w * tb.Cs + s], c1 = col[(size_t)(w + 1) * tb.Cs + s];
       v0 += a0 * x[c0];
       v1 += a1 * x[c1];
     }
-    if (w < tb.lat_w) v0 += tb.lat_val[(size_t)w * tb.Cs + s] * x[tb.lat_col[(size_t)w * tb.Cs + s]];
+    if (w < tb.lat_w) v0 += val[(size_t)w * tb.Cs + s] * x[col[(size_t)w * tb.Cs + s]];
     use(s, v0 + v1);
   }
 }

@@ -133,6 +133,7 @@ int build_tables(int p, DevTables **out) {
     }
   }
   tb.lat_w = W;
+  tb.lat_lds = (size_t)W * Cs * 12 <= 48 * 1024 ? 1 : 0;
   int rc = 0;
   rc |= upload(dt, rec, &tb.rec);
   rc |= upload(dt, wl2p, &tb.wl2p);
@@ -201,7 +202,7 @@ void make_layout(int64_t n, int levels, int p, Layout &ly) {
   sz[O_STATUS] = 4 * 8;
   sz[O_SCRATCH] = 8 * 64;
   sz[O_MBOX] = 8 * 64;
-  sz[O_SYNC] = 4 * 64;
+  sz[O_SYNC] = 4 * 512;
   const int NG = NT / group_size(p);
   sz[O_RED] = 8 * ((n + NG - 1) / NG + 64);
   sz[O_STAGE] = 8 * 4 * n;
@@ -237,8 +238,9 @@ struct fmm_mc_ctx {
 
 namespace {
 
-size_t smem_bytes(int GS, int Cs) {
-  return GS == 16 ? Lds<16>::bytes(Cs) : Lds<32>::bytes(Cs);
+size_t smem_bytes(int GS, const Tabs &tb) {
+  int w = tb.lat_lds ? tb.lat_w : 0;
+  return GS == 16 ? Lds<16>::bytes(tb.Cs, w) : Lds<32>::bytes(tb.Cs, w);
 }
 
 int grid_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
@@ -249,10 +251,10 @@ int run_setup_kernels(fmm_mc_ctx *h) {
   hipStream_t st = h->stream;
   const int L = ch.L;
   const long long nleaf = 1LL << (3 * h->levels);
-  const size_t shm = smem_bytes(h->GS, h->Cs);
+  const size_t shm = smem_bytes(h->GS, h->tables->tabs);
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nleaf, NT)), dim3(NT), 0, st, ch.bin_cnt, 0, nleaf);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, ch.status, 0, 8);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, (int *)ch.sync, 0, 64);
+  hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(NT), 0, st, (int *)ch.sync, 0, 512);
   hipLaunchKernelGGL(k_stage, dim3(grid_for(h->n, NT)), dim3(NT), 0, st, ch);
   hipLaunchKernelGGL(k_bin_finalize, dim3(grid_for(nleaf, NT)), dim3(NT), 0, st, ch, (int)nleaf);
   const int NG = NT / h->GS;
@@ -382,6 +384,7 @@ int fmm_mc_setup(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_stream,
   ch.B = ly.B;
   ch.mixed = (flags & FMM_MC_MIXED) ? 1 : 0;
   ch.a = box;
+  for (int l = 0; l <= MAXL + 1; ++l) ch.inv_h[l] = double(1LL << (l > 0 ? l - 1 : 0)) / box;
   ch.px = (double *)(w + ly.off[O_PX]);
   ch.py = (double *)(w + ly.off[O_PY]);
   ch.pz = (double *)(w + ly.off[O_PZ]);
@@ -490,7 +493,7 @@ int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
   if (!new_pos || !dE || !finite3(new_pos)) return FMM_MC_EINVAL;
   if (idx < 0 || idx >= h->n) return FMM_MC_ERANGE;
   const Tabs &tb = h->tables->tabs;
-  const size_t shm = smem_bytes(h->GS, h->Cs);
+  const size_t shm = smem_bytes(h->GS, h->tables->tabs);
   if (h->GS == 16)
     hipLaunchKernelGGL(k_propose_one<16>, dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
                        new_pos[1], new_pos[2]);
@@ -518,7 +521,7 @@ int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *
     if (rc) return rc;
   }
   const Tabs &tb = h->tables->tabs;
-  const size_t shm = smem_bytes(h->GS, h->Cs);
+  const size_t shm = smem_bytes(h->GS, h->tables->tabs);
   const int NG = NT / h->GS;
   const int nb = accept_blocks(h->ch.L, NG);
   if (h->GS == 16) {
@@ -554,7 +557,7 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   hipStream_t st = h0->stream;
   const Tabs &tb = h0->tables->tabs;
   const int GS = h0->GS;
-  const size_t shm = smem_bytes(GS, h0->Cs);
+  const size_t shm = smem_bytes(GS, tb);
   // device scratch for per-chain parameters: the first chain's workspace
   // stats area holds max_step (n_chains <= 4096 supported through a
   // temporary allocation otherwise)
@@ -593,11 +596,11 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   rp.tr_leaf = tr_leaf;
   rp.stats = d_stats;
   bool single = (n_chains == 1 && mode != 1);
-  if (single) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 64);
+  if (single) hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 512);
   HIPCHK(hipEventRecord(h0->ev0, st));
   if (single) {
     const int NG = NT / GS;
-    int G = accept_blocks(h0->ch.L, NG);
+    int G = accept_blocks(h0->ch.L, NG) + 1;  // workgroup 0 proposes, the others update
     int ncu = 0, per = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
     if (GS == 16)

@@ -18,24 +18,77 @@ struct Move {
   int c1[MAXL + 1][3];  // cell of rn on each level
 };
 
-__device__ __forceinline__ void locate_move(const Chain &ch, Move &mv) {
-  for (int l = 1; l <= ch.L; ++l) {
-    int n = 1 << (l - 1);
-    for (int k = 0; k < 3; ++k) {
-      mv.c0[l][k] = cell_coord(mv.r[k], ch.a, n);
-      mv.c1[l][k] = cell_coord(mv.rn[k], ch.a, n);
-    }
-  }
-}
-
 __device__ __forceinline__ int lin3(int n, int x, int y, int z) { return x + n * (y + n * z); }
 __device__ __forceinline__ int imod(int i, int n) { return ((i % n) + n) % n; }
 __device__ __forceinline__ int ifloordiv(int i, int n) { return (i - imod(i, n)) / n; }
 
-// copy the recurrence constants into LDS (all threads; caller syncs)
+// cells of r and rn on every level, one level per thread (caller syncs)
+__device__ __forceinline__ void locate_move_par(const Chain &ch, Move &mv) {
+  const int l = threadIdx.x + 1;
+  if (l <= ch.L) {
+    int n = 1 << (l - 1);
+    for (int k = 0; k < 3; ++k) {
+      mv.c0[l][k] = cell_coord(mv.r[k], ch.inv_h[l], n);
+      mv.c1[l][k] = cell_coord(mv.rn[k], ch.inv_h[l], n);
+    }
+  }
+}
+
+// indices into Lds::ints
+enum : int {
+  I_NCELL = 0,     // 54 near cells
+  I_NSHIFT = 54,   // 54 image shifts
+  I_MASK = 108,    // images of the moving charge met in the new near region
+  I_SLOTK = 109,   // slot of the moving charge in its leaf bin
+  I_CNTOLD = 110,  // occupancy of the old leaf bin
+  I_CNTNEW = 111,  // occupancy of the new leaf bin
+  I_IDLAST = 112,  // particle in the last slot of the old leaf bin
+  I_FLAG = 113,
+  I_LIST = 128     // candidate list of a coarse accept block (55 entries)
+};
+
+// Load the constant tables and the chain's small state into LDS (all
+// threads; caller syncs).
 template <int GS>
-__device__ __forceinline__ void stage_rec(const Tabs &tb, Lds<GS> &sm) {
-  for (int i = threadIdx.x; i < 3 * tb.Cs; i += NT) sm.rec[i] = tb.rec[i];
+__device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<GS> &sm, bool state) {
+  const int Cs = tb.Cs;
+  for (int i = threadIdx.x; i < 3 * Cs; i += NT) sm.rec[i] = tb.rec[i];
+  for (int i = threadIdx.x; i < Cs; i += NT) {
+    sm.wl2p[i] = tb.wl2p[i];
+    sm.wdot[i] = tb.wdot[i];
+    sm.sgnc[i] = tb.sgnc[i];
+    if (state) {
+      sm.H[i] = ch.H[i];
+      sm.K[i] = ch.K[i];
+    }
+  }
+  if (tb.lat_lds)
+    for (int i = threadIdx.x; i < tb.lat_w * Cs; i += NT) {
+      sm.lat_val[i] = tb.lat_val[i];
+      sm.lat_col[i] = tb.lat_col[i];
+    }
+  if (state && threadIdx.x < 3) sm.st[threadIdx.x] = ch.dip[threadIdx.x];
+  if (state && threadIdx.x == 3) sm.st[3] = ch.U[0];
+}
+
+// write the chain's small state back to global memory (all threads)
+template <int GS>
+__device__ __forceinline__ void writeback_lds(const Chain &ch, const Tabs &tb, Lds<GS> &sm) {
+  for (int i = threadIdx.x; i < tb.C; i += NT) {
+    ch.H[i] = sm.H[i];
+    ch.K[i] = sm.K[i];
+  }
+  if (threadIdx.x < 3) ch.dip[threadIdx.x] = sm.st[threadIdx.x];
+  if (threadIdx.x == 3) ch.U[0] = sm.st[3];
+}
+
+template <int GS>
+__device__ __forceinline__ const double *lat_val_of(const Tabs &tb, Lds<GS> &sm) {
+  return tb.lat_lds ? sm.lat_val : tb.lat_val;
+}
+template <int GS>
+__device__ __forceinline__ const int *lat_col_of(const Tabs &tb, Lds<GS> &sm) {
+  return tb.lat_lds ? sm.lat_col : tb.lat_col;
 }
 
 struct ProposeOut {
@@ -51,45 +104,67 @@ struct ProposeOut {
 //      + q [Psi^inf(r') - Psi^inf(r)] + 1/2 dk.R(dk)                   (far lattice)
 //      - (2 pi/3V)(|D + q(r'-r)|^2 - |D|^2)                            (tin-foil)
 // The new-side direct sum leaves out every image of the moving charge in
-// the near region together with the matching self term (they cancel).
-template <int GS>
-__device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS> &sm) {
+// the near region together with the matching self term (they cancel). The
+// bin records the bookkeeping of an accept needs are kept in LDS. `spare`
+// is run by the last wavefront while the others evaluate the expansions.
+template <int GS, typename Spare>
+__device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS> &sm,
+                                 Spare &&spare) {
   constexpr int NG = NT / GS, PM = PmaxOf<GS>::v;
+  constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   const int Cs = tb.Cs, C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
-  int *ncell = sm.ints, *nshift = sm.ints + 54, *npre = sm.ints + 108, *nmask = sm.ints + 164;
-
+  int *ints = sm.ints;
   const double a = ch.a, q = mv.q;
-  const int L = ch.L, d = ch.d;
+  const int L = ch.L, d = ch.d, B = ch.B;
   const int npts = 2 * d + 2;
+  const int nL = 1 << (L - 1);
 
-  // near-field cell list (54 entries: 27 around the old leaf, 27 around the new)
-  if (t < 54) {
-    int side = t / 27, e = t % 27;
-    int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
+  // ---- near field: 4 threads per near cell, first slot loaded with the count
+  double dold = 0.0, dnew = 0.0;
+  int singular = 0;
+  if (t == 0) ints[I_MASK] = 0;
+  if (t < 216) {
+    const int e = t >> 2, j0 = t & 3;
+    const int side = e / 27, ee = e % 27;
     const int *c = side ? mv.c1[L] : mv.c0[L];
-    int n = 1 << (L - 1);
-    int b[3] = {c[0] + ex, c[1] + ey, c[2] + ez};
-    int s = lin3(n, imod(b[0], n), imod(b[1], n), imod(b[2], n));
-    int w = (ifloordiv(b[0], n) + 1) + 3 * (ifloordiv(b[1], n) + 1) + 9 * (ifloordiv(b[2], n) + 1);
-    ncell[t] = s;
-    nshift[t] = w;
-    int cnt = ch.bin_cnt[s];
-    npre[t + 1] = cnt;  // counts, turned into a prefix sum below
-  }
-  if (t == 0) nmask[0] = 0;
-  __syncthreads();
-  if (t < 64) {  // inclusive scan of the 54 counts in wave 0
-    int v = t < 54 ? npre[t + 1] : 0;
-    for (int o = 1; o < 64; o <<= 1) {
-      int u = __shfl_up(v, o, 64);
-      if (t >= o) v += u;
+    int b[3] = {c[0] + ee % 3 - 1, c[1] + (ee / 3) % 3 - 1, c[2] + ee / 9 - 1};
+    const int cell = lin3(nL, imod(b[0], nL), imod(b[1], nL), imod(b[2], nL));
+    const int fx = ifloordiv(b[0], nL), fy = ifloordiv(b[1], nL), fz = ifloordiv(b[2], nL);
+    const int w = (fx + 1) + 3 * (fy + 1) + 9 * (fz + 1);
+    const double sx = fx * a, sy = fy * a, sz = fz * a;
+    const size_t base = (size_t)cell * B;
+    const int cnt = ch.bin_cnt[cell];
+    int id = ch.bin_id[base + j0];
+    double4 pj = ch.bin_p[base + j0];
+    if (ee == 13 && j0 == 0) ints[side ? I_CNTNEW : I_CNTOLD] = cnt;
+    const double *x = side ? mv.rn : mv.r;
+    for (int j = j0; j < cnt; j += 4) {
+      if (j != j0) {
+        id = ch.bin_id[base + j];
+        pj = ch.bin_p[base + j];
+      }
+      if (side == 0 && ee == 13) {  // the moving charge's own leaf bin
+        if (id == mv.idx) ints[I_SLOTK] = j;
+        if (j == cnt - 1) {
+          ints[I_IDLAST] = id;
+          sm.stash[0] = pj;
+        }
+      }
+      if (id == mv.idx) {
+        if (side) atomicOr(&ints[I_MASK], 1 << w);
+        if (side || w == 13) continue;  // w == 13: no image shift
+      }
+      double dx = x[0] - (pj.x + sx), dy = x[1] - (pj.y + sy), dz = x[2] - (pj.z + sz);
+      double r2 = dx * dx + dy * dy + dz * dz;
+      if (side && r2 == 0.0) singular = 1;
+      double v = pj.w / sqrt(r2);
+      if (side) dnew += v; else dold += v;
     }
-    if (t < 54) npre[t + 1] = v;
-    if (t == 0) npre[0] = 0;
   }
 
-  // local expansions at the 2d level points and the two lattice points
+  // ---- local expansions at the 2d level points and the two lattice points
+  const bool spare_in_loop = npts <= NG - 64 / GS;  // the last wavefront has no point
   for (int base = 0; base < npts; base += NG) {
     int pt = base + g;
     if (pt < npts) {
@@ -101,7 +176,7 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
         const double *r = pt ? mv.rn : mv.r;
         hh = a;
         for (int k = 0; k < 3; ++k) x[k] = (r[k] - 0.5 * a) / a;
-        src = ch.H;
+        src = sm.H;
       } else {
         int l = 2 + (pt - 2) / 2, side = (pt - 2) % 2;
         buf = sm.gbuf + (size_t)g * Cs;
@@ -113,65 +188,43 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
         src = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
       }
       // the expansion coefficients are loaded while the harmonics are formed
-      double lv[(PmaxOf<GS>::v + 1) * (PmaxOf<GS>::v + 1) / GS + 1];
+      double lv[NJ];
 #pragma unroll
-      for (int j = 0; j < (PM + 1) * (PM + 1) / GS + 1; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         int s = lane + j * GS;
-        lv[j] = s < C ? src[s] * tb.wl2p[s] : 0.0;
+        lv[j] = s < C ? src[s] : 0.0;
       }
       group_harmonics<GS, PM, 0, false>(lane, tb, sm.rec, x[0], x[1], x[2], 1.0, buf);
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       double acc = 0.0;
 #pragma unroll
-      for (int j = 0; j < (PM + 1) * (PM + 1) / GS + 1; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         int s = lane + j * GS;
-        if (s < C) acc += lv[j] * buf[s];
+        if (s < C) acc += lv[j] * sm.wl2p[s] * buf[s];
       }
       acc = group_sum<GS>(acc);
       if (lane == 0) sm.vals[pt] = acc / hh;
+    } else if (base == 0 && spare_in_loop && t >= NT - 64) {
+      spare(t - (NT - 64));
     }
     __syncthreads();
   }
+  if (!spare_in_loop && t >= NT - 64) spare(t - (NT - 64));
 
-  // direct near field
-  double dold = 0.0, dnew = 0.0;
-  int singular = 0;
-  const int total = npre[54];
-  for (int i = t; i < total; i += NT) {
-    int lo = 0, hi = 54;  // entry e with npre[e] <= i < npre[e+1]
-    while (hi - lo > 1) {
-      int mid = (lo + hi) >> 1;
-      if (npre[mid] <= i) lo = mid; else hi = mid;
-    }
-    int e = lo, j = i - npre[e];
-    int side = e / 27, cell = ncell[e], w = nshift[e];
-    double sx = (w % 3 - 1) * a, sy = ((w / 3) % 3 - 1) * a, sz = (w / 9 - 1) * a;
-    int id = ch.bin_id[(size_t)cell * ch.B + j];
-    double4 pj = ch.bin_p[(size_t)cell * ch.B + j];
-    const double *x = side ? mv.rn : mv.r;
-    if (id == mv.idx) {
-      if (side) atomicOr(&nmask[0], 1 << w);
-      if (side || w == 13) continue;  // w == 13: no image shift
-    }
-    double dx = x[0] - (pj.x + sx), dy = x[1] - (pj.y + sy), dz = x[2] - (pj.z + sz);
-    double r2 = dx * dx + dy * dy + dz * dz;
-    if (side && r2 == 0.0) singular = 1;
-    double v = pj.w / sqrt(r2);
-    if (side) dnew += v; else dold += v;
-  }
-  // far lattice quadratic term: dk = q (conj T(r') - conj T(r)), 1/2 dk.R(dk)
-  for (int s = t; s < C; s += NT) sm.dk[s] = q * tb.sgnc[s] * (sm.latN[s] - sm.latO[s]);
+  // ---- far lattice quadratic term: dk = q (conj T(r') - conj T(r)), 1/2 dk.R(dk)
+  for (int s = t; s < C; s += NT) sm.dk[s] = q * sm.sgnc[s] * (sm.latN[s] - sm.latO[s]);
   __syncthreads();
   // self-interaction with the old position's images (Sec. 3.4)
   double self = 0.0;
-  if (t < 27 && !((nmask[0] >> t) & 1)) {
+  if (t < 27 && !((ints[I_MASK] >> t) & 1)) {
     double sx = (t % 3 - 1) * a, sy = ((t / 3) % 3 - 1) * a, sz = (t / 9 - 1) * a;
     double dx = mv.rn[0] - (mv.r[0] + sx), dy = mv.rn[1] - (mv.r[1] + sy), dz = mv.rn[2] - (mv.r[2] + sz);
     self = q * q / sqrt(dx * dx + dy * dy + dz * dz);
   }
   double quad = 0.0;
-  lattice_rows(tb, sm.dk, [&](int s, double v) { quad += tb.wdot[s] * sm.dk[s] * v; });
+  lattice_rows(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk,
+               [&](int s, double v) { quad += sm.wdot[s] * sm.dk[s] * v; });
   double part[4] = {dold, dnew, self, quad};
   wg_sum4(part, sm.red);
   int sing = __syncthreads_or(singular);
@@ -186,7 +239,7 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
   dE += -part[2] + q * q / a * tb.self_const;
   dE += q * (sm.vals[1] - sm.vals[0]) + 0.5 * part[3] / a;
   double dr[3] = {mv.rn[0] - mv.r[0], mv.rn[1] - mv.r[1], mv.rn[2] - mv.r[2]};
-  double Ddot = ch.dip[0] * dr[0] + ch.dip[1] * dr[1] + ch.dip[2] * dr[2];
+  double Ddot = sm.st[0] * dr[0] + sm.st[1] * dr[1] + sm.st[2] * dr[2];
   double dd = dr[0] * dr[0] + dr[1] * dr[1] + dr[2] * dr[2];
   dE += -2.0 * M_PI / (3.0 * a * a * a) * (2.0 * q * Ddot + q * q * dd);
   out.dE = dE;
@@ -230,10 +283,11 @@ __device__ __forceinline__ bool image_in_il(const int s[3], const int c[3], int 
 template <int GS>
 __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS> &sm) {
   constexpr int NG = NT / GS, PM = PmaxOf<GS>::v;
+  constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   const int Cs = tb.Cs, C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
   double *acc = sm.gbuf;  // NG * Cs
-  int *lst = sm.ints;     // candidate list
+  int *lst = sm.ints + I_LIST;
   const double a = ch.a, q = mv.q;
   const int L = ch.L;
 
@@ -250,6 +304,8 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
     const int l = coarse_l, n = 1 << (l - 1);
     const double h = a / n;
     int s[3] = {s_lin % n, (s_lin / n) % n, s_lin / (n * n)};
+    double *dst = ch.Ld + ch.ld_off[l] + (size_t)s_lin * Cs;
+    double old = t < C ? dst[t] : 0.0;  // C <= NT for the 16-lane groups
     if (t < 64) {
       bool valid = false;
       int side = t / 27, e = t % 27;
@@ -289,11 +345,10 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
                                        acc + (size_t)g * Cs);
     }
     __syncthreads();
-    double *dst = ch.Ld + ch.ld_off[l] + (size_t)s_lin * Cs;
     for (int k = t; k < C; k += NT) {
       double sum = 0.0;
       for (int gg = 0; gg < NG; ++gg) sum += acc[(size_t)gg * Cs + k];
-      dst[k] += sum;
+      dst[k] = (k == t ? old : dst[k]) + sum;
     }
     __syncthreads();
     return;
@@ -317,13 +372,13 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
     bool other = image_in_il(s, co, n, b_other);
     if (side == 1 && other) return;  // owned by the old-side item
     double *buf = acc + (size_t)g * Cs;
-    const double *dstc = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * Cs;
+    double *dst = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * Cs;
     // the target's coefficients are loaded while the harmonics are formed
-    double old[(PmaxOf<GS>::v + 1) * (PmaxOf<GS>::v + 1) / GS + 1];
+    double old[NJ];
 #pragma unroll
-    for (int j = 0; j < (PM + 1) * (PM + 1) / GS + 1; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       int k = lane + j * GS;
-      old[j] = k < C ? dstc[k] : 0.0;
+      old[j] = k < C ? dst[k] : 0.0;
     }
     const double *x = side ? mv.rn : mv.r;
     double v[3];
@@ -336,63 +391,56 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    double *dst = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * Cs;
 #pragma unroll
-    for (int j = 0; j < (PM + 1) * (PM + 1) / GS + 1; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       int k = lane + j * GS;
       if (k < C) dst[k] = old[j] + buf[k];
     }
   }
 }
 
-// Bookkeeping of an accepted move by one workgroup: K += dk, H += R(dk),
-// dipole, running energy, position and leaf bins (Sec. 3.4; the particle
-// to cell map of Sec. 5.2). Returns nonzero on bin overflow.
+// Bookkeeping of an accepted move by one workgroup, on the LDS copies of
+// K, H, dipole and running energy: K += dk, H += R(dk) (Sec. 3.4), and the
+// position and leaf bins (the particle to cell map of Sec. 5.2), from the
+// bin records kept in LDS (I_SLOTK, I_CNTOLD, I_CNTNEW, I_IDLAST, stash[0]).
+// Returns nonzero on bin overflow.
 template <int GS>
 __device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &mv, double dE, Lds<GS> &sm) {
   constexpr int PM = PmaxOf<GS>::v;
   const int C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
-  int *flag = sm.ints + 200;
+  int *ints = sm.ints;
   const double a = ch.a, q = mv.q;
   if (g < 2) {
     const double *r = g ? mv.rn : mv.r;
     group_harmonics<GS, PM, 1, false>(lane, tb, sm.rec, (r[0] - 0.5 * a) / a, (r[1] - 0.5 * a) / a,
                                       (r[2] - 0.5 * a) / a, 1.0, g ? sm.latN : sm.latO);
   }
-  __syncthreads();
-  for (int s = t; s < C; s += NT) {
-    sm.dk[s] = q * (sm.latN[s] - sm.latO[s]);
-    ch.K[s] += sm.dk[s];
-  }
-  __syncthreads();
-  lattice_rows(tb, sm.dk, [&](int s, double v) { ch.H[s] += v; });
-  if (t == 0) {
+  if (t == NT - 1) {  // bins and position: stores only
     int ovf = 0;
-    for (int k = 0; k < 3; ++k) ch.dip[k] += q * (mv.rn[k] - mv.r[k]);
-    ch.U[0] += dE;
     const int L = ch.L, n = 1 << (L - 1), B = ch.B;
-    int k = mv.idx;
-    int oldc = ch.leaf_of[k];
-    int newc = lin3(n, mv.c1[L][0], mv.c1[L][1], mv.c1[L][2]);
-    int sl = ch.slot_of[k];
+    const int k = mv.idx;
+    const int oldc = lin3(n, mv.c0[L][0], mv.c0[L][1], mv.c0[L][2]);
+    const int newc = lin3(n, mv.c1[L][0], mv.c1[L][1], mv.c1[L][2]);
+    const int sl = ints[I_SLOTK];
+    const double4 rec = make_double4(mv.rn[0], mv.rn[1], mv.rn[2], q);
     if (oldc == newc) {
-      ch.bin_p[(size_t)oldc * B + sl] = make_double4(mv.rn[0], mv.rn[1], mv.rn[2], q);
+      ch.bin_p[(size_t)oldc * B + sl] = rec;
     } else {
-      int cnt = ch.bin_cnt[newc];
+      const int cnt = ints[I_CNTNEW];
       if (cnt >= B) {
         ovf = 1;
       } else {
-        int last = ch.bin_cnt[oldc] - 1;
+        const int last = ints[I_CNTOLD] - 1;
         if (sl != last) {
-          int moved = ch.bin_id[(size_t)oldc * B + last];
+          const int moved = ints[I_IDLAST];
           ch.bin_id[(size_t)oldc * B + sl] = moved;
-          ch.bin_p[(size_t)oldc * B + sl] = ch.bin_p[(size_t)oldc * B + last];
+          ch.bin_p[(size_t)oldc * B + sl] = sm.stash[0];
           ch.slot_of[moved] = sl;
         }
         ch.bin_cnt[oldc] = last;
         ch.bin_id[(size_t)newc * B + cnt] = k;
-        ch.bin_p[(size_t)newc * B + cnt] = make_double4(mv.rn[0], mv.rn[1], mv.rn[2], q);
+        ch.bin_p[(size_t)newc * B + cnt] = rec;
         ch.bin_cnt[newc] = cnt + 1;
         ch.slot_of[k] = cnt;
         ch.leaf_of[k] = newc;
@@ -402,13 +450,40 @@ __device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &m
       ch.px[k] = mv.rn[0];
       ch.py[k] = mv.rn[1];
       ch.pz[k] = mv.rn[2];
+      for (int j = 0; j < 3; ++j) sm.st[j] += q * (mv.rn[j] - mv.r[j]);
+      sm.st[3] += dE;
     }
-    flag[0] = ovf;
+    ints[I_FLAG] = ovf;
   }
   __syncthreads();
-  int ovf = flag[0];
+  for (int s = t; s < C; s += NT) {
+    sm.dk[s] = q * (sm.latN[s] - sm.latO[s]);
+    sm.K[s] += sm.dk[s];
+  }
+  __syncthreads();
+  lattice_rows(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk, [&](int s, double v) { sm.H[s] += v; });
+  __syncthreads();
+  int ovf = ints[I_FLAG];
   __syncthreads();
   return ovf;
+}
+
+// the bin records of the bookkeeping, read from global memory (for an
+// accept that was not preceded by this workgroup's proposal)
+template <int GS>
+__device__ void load_bin_records(const Chain &ch, const Move &mv, Lds<GS> &sm) {
+  if (threadIdx.x == 0) {
+    const int L = ch.L, n = 1 << (L - 1), B = ch.B;
+    const int oldc = lin3(n, mv.c0[L][0], mv.c0[L][1], mv.c0[L][2]);
+    const int newc = lin3(n, mv.c1[L][0], mv.c1[L][1], mv.c1[L][2]);
+    int *ints = sm.ints;
+    ints[I_SLOTK] = ch.slot_of[mv.idx];
+    ints[I_CNTOLD] = ch.bin_cnt[oldc];
+    ints[I_CNTNEW] = ch.bin_cnt[newc];
+    int last = ints[I_CNTOLD] - 1;
+    ints[I_IDLAST] = ch.bin_id[(size_t)oldc * B + last];
+    sm.stash[0] = ch.bin_p[(size_t)oldc * B + last];
+  }
 }
 
 }  // namespace fmmdev

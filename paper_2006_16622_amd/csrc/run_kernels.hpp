@@ -6,15 +6,18 @@
 //    chains of uneven size and depth in one launch (the paper's "several
 //    Markov chains in parallel", Sec. 6).
 //  * k_run_single: one chain on many workgroups (cooperative launch, all
-//    co-resident). Workgroup 0 proposes and decides; on accept it posts the
-//    move in a mailbox and the update blocks of Alg. L.2 are shared out over
-//    all workgroups, each owning distinct target cells, then workgroup 0
-//    waits for their completion before the next proposal. The per-level
-//    work is spread as the paper suggests for parallelism (Sec. 6).
+//    co-resident). Workgroup 0 proposes, decides and keeps the bookkeeping;
+//    on accept it posts the move in a mailbox and the update blocks of
+//    Alg. L.2, each owning distinct target cells, are shared out over the
+//    other workgroups; workgroup 0 waits for their completion before the
+//    next proposal. The per-level work is spread as the paper suggests for
+//    parallelism (Sec. 6).
 //
 // A step draws (idx, delta, u) from Philox4x64-10 (key = (seed, chain),
 // counter = (t, 0|1, 0, 0)) or reads them from fixed lists; the move is
-// accepted iff u < exp(-beta dE) and it is not singular.
+// accepted iff u < exp(-beta dE) and it is not singular. The draw of step
+// t+1 and the record of its particle are fetched by an idle wavefront while
+// step t is being proposed.
 #pragma once
 
 #include "mc_step.hpp"
@@ -35,33 +38,50 @@ struct RunParams {
   double *tr_pos, *tr_dE;
   uint8_t *tr_acc;
   int32_t *tr_leaf;
-  double *stats;           // per chain 8 doubles: proposed, accepted, singular, dE_sum, status
+  double *stats;           // per chain 8 doubles: proposed, accepted, singular, dE_sum, status, times
 };
 
-__device__ __forceinline__ void draw_step(const RunParams &rp, int c, int64_t t, int64_t N, double D,
-                                          int64_t &idx, double rn_abs[3], const Chain &ch,
-                                          double &u) {
-#pragma clang fp contract(off)
+// the draw of one step and the record of its particle (LDS)
+struct NextDraw {
+  int64_t idx;
+  double d[3];   // displacement (Philox) or absolute new position (list)
+  double u;
+  double r[3];   // particle position when fetched
+  double q;
+};
+
+__device__ __forceinline__ void draw_into(const RunParams &rp, int c, int64_t t, const Chain &ch, double D,
+                                          NextDraw &nd) {
   if (rp.list_idx) {
-    idx = rp.list_idx[t];
-    for (int k = 0; k < 3; ++k) rn_abs[k] = rp.list_pos[3 * t + k];
-    u = rp.list_u[t];
+    nd.idx = rp.list_idx[t];
+    for (int k = 0; k < 3; ++k) nd.d[k] = rp.list_pos[3 * t + k];
+    nd.u = rp.list_u[t];
   } else {
-    double delta[3];
-    mh_draw(rp.seed, (uint64_t)c, (uint64_t)(rp.t0 + t), N, D, idx, delta, u);
-    double r[3] = {ch.px[idx], ch.py[idx], ch.pz[idx]};
-    for (int k = 0; k < 3; ++k) rn_abs[k] = r[k] + delta[k];
+    mh_draw(rp.seed, (uint64_t)c, (uint64_t)(rp.t0 + t), ch.N, D, nd.idx, nd.d, nd.u);
   }
+  nd.r[0] = ch.px[nd.idx];
+  nd.r[1] = ch.py[nd.idx];
+  nd.r[2] = ch.pz[nd.idx];
+  nd.q = ch.pq[nd.idx];
 }
 
-__device__ __forceinline__ void fill_move(const Chain &ch, Move &mv, int64_t idx, const double rn_abs[3]) {
-  mv.idx = (int)idx;
-  mv.q = ch.pq[idx];
-  mv.r[0] = ch.px[idx];
-  mv.r[1] = ch.py[idx];
-  mv.r[2] = ch.pz[idx];
-  for (int k = 0; k < 3; ++k) mv.rn[k] = wrap_coord(rn_abs[k], ch.a);
-  locate_move(ch, mv);
+// Build the move of a step from its draw (thread 0). If the previous step
+// accepted a move of the same particle after the draw was fetched, its new
+// position replaces the fetched one.
+__device__ __forceinline__ void move_from_draw(const RunParams &rp, const Chain &ch, const NextDraw &nd,
+                                               bool prev_acc, int prev_idx, const double prev_rn[3],
+                                               Move &mv) {
+#pragma clang fp contract(off)
+  double r[3];
+  const bool moved = prev_acc && prev_idx == (int)nd.idx;
+  for (int k = 0; k < 3; ++k) r[k] = moved ? prev_rn[k] : nd.r[k];
+  mv.idx = (int)nd.idx;
+  mv.q = nd.q;
+  for (int k = 0; k < 3; ++k) {
+    mv.r[k] = r[k];
+    double rn_abs = rp.list_idx ? nd.d[k] : r[k] + nd.d[k];
+    mv.rn[k] = wrap_coord(rn_abs, ch.a);
+  }
 }
 
 template <int GS>
@@ -69,29 +89,36 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
   __shared__ Move mv;
-  __shared__ int s_acc, s_ovf;
-  __shared__ double s_dE;
+  __shared__ NextDraw nd;
+  __shared__ int s_acc;
+  __shared__ double s_u;
   const int c = blockIdx.x, t = threadIdx.x;
   const Chain ch = chains[c];
-  Lds<GS> sm(lds, tb.Cs);
-  stage_rec(tb, sm);
+  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  stage_lds(ch, tb, sm, true);
   const double D = rp.max_step[c];
   const int nblk = accept_blocks(ch.L, NG);
   double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
   uint64_t tick_prop = 0, tick_acc = 0;
   int status = 0;
+  bool prev_acc = false;
+  int prev_idx = -1;
+  double prev_rn[3] = {0, 0, 0};
+  if (t == 0 && rp.steps > 0) draw_into(rp, c, 0, ch, D, nd);
+  __syncthreads();
   for (int64_t step = 0; step < rp.steps; ++step) {
     uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
     if (t == 0) {
-      int64_t idx;
-      double rn_abs[3], u;
-      draw_step(rp, c, step, ch.N, D, idx, rn_abs, ch, u);
-      fill_move(ch, mv, idx, rn_abs);
-      s_dE = u;  // park u
+      move_from_draw(rp, ch, nd, prev_acc, prev_idx, prev_rn, mv);
+      s_u = nd.u;
     }
     __syncthreads();
-    double u = s_dE;
-    ProposeOut po = propose_wg<GS>(ch, tb, mv, sm);
+    locate_move_par(ch, mv);
+    __syncthreads();
+    const double u = s_u;
+    ProposeOut po = propose_wg<GS>(ch, tb, mv, sm, [&](int lane) {
+      if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
+    });
     uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
     tick_prop += t_1 - t_0;
     if (t == 0) {
@@ -111,7 +138,10 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
       }
     }
     __syncthreads();
-    if (s_acc) {
+    prev_acc = s_acc;
+    prev_idx = mv.idx;
+    for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
+    if (prev_acc) {
       for (int b = 0; b < nblk; ++b) {
         accept_block<GS>(ch, tb, mv, b, sm);
         __syncthreads();
@@ -128,6 +158,8 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
       }
     }
   }
+  __syncthreads();
+  writeback_lds(ch, tb, sm);
   if (t == 0) {
     double *st = rp.stats + 8 * c;
     st[0] = nprop;
@@ -161,11 +193,15 @@ __device__ __forceinline__ bool spin_until_ne(unsigned *p, unsigned old, unsigne
     __builtin_amdgcn_s_sleep(1);
   }
 }
-__device__ __forceinline__ bool spin_until_ge(unsigned *p, unsigned target, uint64_t limit) {
+// wavefront 0 waits until flags[1..G-1] all equal `target` (one flag per
+// helper workgroup, so the completions do not contend on one address)
+__device__ __forceinline__ bool spin_all_equal(unsigned *flags, int G, unsigned target, uint64_t limit) {
+  const int lane = threadIdx.x & 63;
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   while (true) {
-    unsigned v = ld_relaxed(p);
-    if ((int)(v - target) >= 0) return true;
+    bool mine = true;
+    for (int w = 1 + lane; w < G; w += 64) mine = mine && (ld_relaxed(&flags[w]) == target);
+    if (__all(mine)) return true;
     if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
     __builtin_amdgcn_s_sleep(1);
   }
@@ -178,36 +214,44 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
   __shared__ Move mv;
+  __shared__ NextDraw nd;
   __shared__ int s_flag, s_acc;
   __shared__ double s_u;
   const int t = threadIdx.x, w = blockIdx.x, G = gridDim.x;
-  Lds<GS> sm(lds, tb.Cs);
-  stage_rec(tb, sm);
-  __syncthreads();
   const int nblk = accept_blocks(ch.L, NG);
-  unsigned *seq = ch.sync, *done = ch.sync + 1, *stop = ch.sync + 2, *err = ch.sync + 3;
+  unsigned *seq = ch.sync, *stop = ch.sync + 2, *err = ch.sync + 3, *doneflag = ch.sync + 64;
   double *mb = ch.mbox;
+  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  stage_lds(ch, tb, sm, w == 0);
+  __syncthreads();
   if (w == 0) {
     const double D = rp.max_step[0];
     double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
     int status = 0;
-    unsigned myseq = 0, expect = 0;
+    unsigned myseq = 0;
     uint64_t tick_prop = 0, tick_acc = 0, tick_wait = 0;
+    bool prev_acc = false;
+    int prev_idx = -1;
+    double prev_rn[3] = {0, 0, 0};
+    if (t == 0 && rp.steps > 0) draw_into(rp, 0, 0, ch, D, nd);
+    __syncthreads();
     for (int64_t step = 0; step < rp.steps; ++step) {
       uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
       if (t == 0) {
-        int64_t idx;
-        double rn_abs[3], u;
-        draw_step(rp, 0, step, ch.N, D, idx, rn_abs, ch, u);
-        fill_move(ch, mv, idx, rn_abs);
-        s_u = u;
+        move_from_draw(rp, ch, nd, prev_acc, prev_idx, prev_rn, mv);
+        s_u = nd.u;
       }
       __syncthreads();
-      ProposeOut po = propose_wg<GS>(ch, tb, mv, sm);
+      locate_move_par(ch, mv);
+      __syncthreads();
+      const double u = s_u;
+      ProposeOut po = propose_wg<GS>(ch, tb, mv, sm, [&](int lane) {
+        if (lane == 0 && step + 1 < rp.steps) draw_into(rp, 0, step + 1, ch, D, nd);
+      });
       uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
       tick_prop += t_1 - t_0;
       if (t == 0) {
-        int acc = !po.singular && (s_u < exp(-rp.beta * po.dE));
+        int acc = !po.singular && (u < exp(-rp.beta * po.dE));
         s_acc = acc;
         nprop += 1;
         nsing += po.singular;
@@ -220,7 +264,7 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
           int n = 1 << (ch.L - 1);
           rp.tr_leaf[step] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
         }
-        if (acc) {
+        if (acc && G > 1) {
           mb[0] = (double)mv.idx;
           mb[1] = mv.q;
           for (int k = 0; k < 3; ++k) {
@@ -230,15 +274,21 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
         }
       }
       __syncthreads();
-      if (s_acc) {
+      prev_acc = s_acc;
+      prev_idx = mv.idx;
+      for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
+      if (prev_acc) {
         if (G > 1) {
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          __syncthreads();
-          if (t == 0) st_release(seq, ++myseq);
-        }
-        for (int b = 0; b < nblk; b += G) {
-          accept_block<GS>(ch, tb, mv, b, sm);
-          __syncthreads();
+          ++myseq;  // every thread keeps the sequence number (wavefront 0 waits on it)
+          if (t == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            st_release(seq, myseq);
+          }
+        } else {
+          for (int b = 0; b < nblk; ++b) {
+            accept_block<GS>(ch, tb, mv, b, sm);
+            __syncthreads();
+          }
         }
         int ovf = accept_bookkeeping<GS>(ch, tb, mv, po.dE, sm);
         if (t == 0) {
@@ -248,8 +298,10 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
         uint64_t t_2 = __builtin_amdgcn_s_memrealtime();
         tick_acc += t_2 - t_1;
         if (G > 1) {
-          expect += (unsigned)(G - 1);
-          if (t == 0) s_flag = spin_until_ge(done, expect, SPIN_LIMIT) ? 0 : 1;
+          if (t < 64) {
+            bool ok = spin_all_equal(doneflag, G, myseq, SPIN_LIMIT);
+            if (t == 0) s_flag = ok ? 0 : 1;
+          }
           __syncthreads();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           if (s_flag) {
@@ -268,6 +320,8 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
       st_release(stop, 1u);
       st_release(seq, ++myseq);
     }
+    __syncthreads();
+    writeback_lds(ch, tb, sm);
     if (t == 0) {
       rp.stats[0] = nprop;
       rp.stats[1] = nacc;
@@ -302,42 +356,53 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
     }
     if (f == 2) return;
     if (t == 0) {
-      double rn_abs[3];
       mv.idx = (int)mb[0];
       mv.q = mb[1];
       for (int k = 0; k < 3; ++k) {
         mv.r[k] = mb[2 + k];
         mv.rn[k] = mb[5 + k];
-        rn_abs[k] = mv.rn[k];
       }
-      (void)rn_abs;
-      locate_move(ch, mv);
     }
     __syncthreads();
-    for (int b = w; b < nblk; b += G) {
+    locate_move_par(ch, mv);
+    __syncthreads();
+    for (int b = w - 1; b < nblk; b += G - 1) {
       accept_block<GS>(ch, tb, mv, b, sm);
       __syncthreads();
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (t == 0) __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == 0) st_release(&doneflag[w], myseq);
   }
 }
 
 // single-call entry points (one proposal / one accept)
+__device__ __forceinline__ void move_direct(const Chain &ch, int64_t idx, double x, double y, double z,
+                                            Move &mv) {
+  if (threadIdx.x == 0) {
+    mv.idx = (int)idx;
+    mv.q = ch.pq[idx];
+    mv.r[0] = ch.px[idx];
+    mv.r[1] = ch.py[idx];
+    mv.r[2] = ch.pz[idx];
+    mv.rn[0] = wrap_coord(x, ch.a);
+    mv.rn[1] = wrap_coord(y, ch.a);
+    mv.rn[2] = wrap_coord(z, ch.a);
+  }
+  __syncthreads();
+  locate_move_par(ch, mv);
+  __syncthreads();
+}
+
 template <int GS>
 __global__ void __launch_bounds__(NT) k_propose_one(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                     double z) {
   extern __shared__ double lds[];
   __shared__ Move mv;
-  Lds<GS> sm(lds, tb.Cs);
-  stage_rec(tb, sm);
-  if (threadIdx.x == 0) {
-    double rn_abs[3] = {x, y, z};
-    fill_move(ch, mv, idx, rn_abs);
-  }
-  __syncthreads();
-  ProposeOut po = propose_wg<GS>(ch, tb, mv, sm);
+  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  stage_lds(ch, tb, sm, true);
+  move_direct(ch, idx, x, y, z, mv);
+  ProposeOut po = propose_wg<GS>(ch, tb, mv, sm, [](int) {});
   if (threadIdx.x == 0) {
     ch.scratch[0] = po.dE;
     ch.scratch[1] = po.singular;
@@ -349,13 +414,9 @@ __global__ void __launch_bounds__(NT) k_accept_blocks(Chain ch, Tabs tb, int64_t
                                                       double z) {
   extern __shared__ double lds[];
   __shared__ Move mv;
-  Lds<GS> sm(lds, tb.Cs);
-  stage_rec(tb, sm);
-  if (threadIdx.x == 0) {
-    double rn_abs[3] = {x, y, z};
-    fill_move(ch, mv, idx, rn_abs);
-  }
-  __syncthreads();
+  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  stage_lds(ch, tb, sm, false);
+  move_direct(ch, idx, x, y, z, mv);
   accept_block<GS>(ch, tb, mv, blockIdx.x, sm);
 }
 
@@ -364,14 +425,13 @@ __global__ void __launch_bounds__(NT) k_accept_book(Chain ch, Tabs tb, int64_t i
                                                     double z, double dE) {
   extern __shared__ double lds[];
   __shared__ Move mv;
-  Lds<GS> sm(lds, tb.Cs);
-  stage_rec(tb, sm);
-  if (threadIdx.x == 0) {
-    double rn_abs[3] = {x, y, z};
-    fill_move(ch, mv, idx, rn_abs);
-  }
+  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  stage_lds(ch, tb, sm, true);
+  move_direct(ch, idx, x, y, z, mv);
+  load_bin_records(ch, mv, sm);
   __syncthreads();
   int ovf = accept_bookkeeping<GS>(ch, tb, mv, dE, sm);
+  writeback_lds(ch, tb, sm);
   if (threadIdx.x == 0 && ovf) ch.status[0] = -7;
 }
 

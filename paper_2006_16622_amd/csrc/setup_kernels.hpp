@@ -32,7 +32,8 @@ __global__ void k_stage(Chain ch) {
   ch.pz[i] = z;
   ch.pq[i] = q;
   int n = 1 << (ch.L - 1);
-  int c = lin3(n, cell_coord(x, ch.a, n), cell_coord(y, ch.a, n), cell_coord(z, ch.a, n));
+  const double inv = ch.inv_h[ch.L];
+  int c = lin3(n, cell_coord(x, inv, n), cell_coord(y, inv, n), cell_coord(z, inv, n));
   ch.leaf_of[i] = c;
   int s = atomicAdd(&ch.bin_cnt[c], 1);
   if (s < ch.B)
@@ -194,7 +195,7 @@ __global__ void k_lattice_init(Chain ch, Tabs tb) {
   const double *M1 = ch.Mp + ch.mp_off[1];
   for (int s = t; s < C; s += NT) ch.K[s] = M1[s];
   __syncthreads();
-  lattice_rows(tb, M1, [&](int s, double v) { ch.H[s] = v; });
+  lattice_rows(tb, tb.lat_val, tb.lat_col, M1, [&](int s, double v) { ch.H[s] = v; });
   double d[3] = {0, 0, 0};
   for (int i = t; i < ch.N; i += NT) {
     d[0] += ch.pq[i] * ch.px[i];
@@ -227,7 +228,7 @@ __global__ void k_energy(Chain ch, Tabs tb) {
       int n = 1 << (l - 1);
       double h = a / n;
       int c[3];
-      for (int k = 0; k < 3; ++k) c[k] = cell_coord(r[k], a, n);
+      for (int k = 0; k < 3; ++k) c[k] = cell_coord(r[k], ch.inv_h[l], n);
       group_harmonics<GS, PmaxOf<GS>::v, 0, false>(lane, tb, tb.rec, (r[0] - (c[0] + 0.5) * h) / h,
                                                    (r[1] - (c[1] + 0.5) * h) / h,
                                                    (r[2] - (c[2] + 0.5) * h) / h, 1.0, buf);
@@ -241,7 +242,7 @@ __global__ void k_energy(Chain ch, Tabs tb) {
     }
     const int n = 1 << (ch.L - 1);
     int c[3];
-    for (int k = 0; k < 3; ++k) c[k] = cell_coord(r[k], a, n);
+    for (int k = 0; k < 3; ++k) c[k] = cell_coord(r[k], ch.inv_h[ch.L], n);
     double dn = 0.0;
     for (int e = lane; e < 27; e += GS) {
       int b[3] = {c[0] + e % 3 - 1, c[1] + (e / 3) % 3 - 1, c[2] + e / 9 - 1};
