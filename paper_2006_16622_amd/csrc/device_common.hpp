@@ -8,15 +8,9 @@
 
 namespace fmmdev {
 
-constexpr int NT = 256;       // threads per workgroup of every kernel
+constexpr int NT = 512;       // threads per workgroup of the Monte Carlo kernels
 constexpr int MAXL = 8;       // levels (depth 7)
 constexpr int NEAR = 27;      // leaf cells of a near region (Alg. 1)
-
-// largest degree of the unrolled harmonic recurrence for a group size
-template <int GS>
-struct PmaxOf {
-  static constexpr int v = GS == 16 ? 15 : 24;
-};
 
 // Constant tables shared by every chain of one degree p on one device.
 struct Tabs {
@@ -188,6 +182,36 @@ __device__ __forceinline__ void mh_draw(uint64_t seed, uint64_t chain, uint64_t 
 // The loops are unrolled to PMAX so that the recurrence constants of the
 // column are all loaded before the dependent arithmetic starts.
 // rec layout: [0, Cs) A(n,m), [Cs, 2Cs) B(n,m) at slot(n,m); [2Cs, 2Cs+p] c_m.
+// lane i of a group receives the value of lane i - O (lanes below O keep
+// their own); DPP row shifts when a group is one 16-lane row
+template <int GS, int O>
+__device__ __forceinline__ double shift_up(double v) {
+  if constexpr (GS == 16) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x110 + O, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x110 + O, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+  } else {
+    return __shfl_up(v, O, GS);
+  }
+}
+
+template <int GS, int O>
+__device__ __forceinline__ void scan_step(int lane, double &wr, double &wi, double &s, bool irregular) {
+  if constexpr (O < GS) {
+    double ur = shift_up<GS, O>(wr), ui = shift_up<GS, O>(wi);
+    double us = irregular ? shift_up<GS, O>(s) : 1.0;
+    if (lane >= O) {
+      double nr = wr * ur - wi * ui;
+      double ni = wr * ui + wi * ur;
+      wr = nr;
+      wi = ni;
+      if (irregular) s *= us;
+    }
+    scan_step<GS, 2 * O>(lane, wr, wi, s, irregular);
+  }
+}
+
 template <int GS, int PMAX, int KIND, bool ACC>
 __device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const double *rec, double x,
                                                 double y, double z, double c, double *buf) {
@@ -201,27 +225,8 @@ __device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const 
     inv_r2 = 1.0 / r2;
     s = m == 0 ? sqrt(inv_r2) : inv_r2;
   }
-#pragma unroll
-  for (int o = 1; o < GS; o <<= 1) {
-    double ur = __shfl_up(wr, o, GS), ui = __shfl_up(wi, o, GS);
-    double us = KIND == 2 ? __shfl_up(s, o, GS) : 1.0;
-    if (lane >= o) {
-      double nr = wr * ur - wi * ui;
-      double ni = wr * ui + wi * ur;
-      wr = nr;
-      wi = ni;
-      if (KIND == 2) s *= us;
-    }
-  }
+  scan_step<GS, 1>(lane, wr, wi, s, KIND == 2);
   if (m > p) return;
-  double Ar[PMAX + 1], Br[PMAX + 1];
-#pragma unroll
-  for (int j = 1; j <= PMAX; ++j) {
-    int n = m + j;
-    int sl = n <= p ? n * n + n + m : 0;
-    Ar[j] = rec[sl];
-    Br[j] = rec[Cs + sl];
-  }
   const double cm = rec[2 * Cs + m];
   double tr = wr * cm, ti = wi * cm;
   double pr = 0.0, pi = 0.0;  // T_{n-2}
@@ -231,7 +236,8 @@ __device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const 
     const int n = m + j;
     if (n <= p) {
       if (j > 0) {
-        double a = Ar[j] * z, b = Br[j] * r2;
+        const int sl = n * n + n + m;
+        double a = rec[sl] * z, b = rec[Cs + sl] * r2;
         double nr = a * tr - b * pr;
         double ni = a * ti - b * pi;
         pr = tr;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -27,6 +28,22 @@ constexpr int LEVELS_MAX = 7;
 
 int pad_cs(int C) { return (C + 15) / 16 * 16; }
 int group_size(int p) { return p + 1 <= 16 ? 16 : 32; }
+
+// Kernel variants: (lanes per group, largest degree of the unrolled
+// harmonic recurrence); the smallest that holds p is used.
+int variant_of(int p) { return p <= 8 ? 0 : p <= 12 ? 1 : p <= 15 ? 2 : 3; }
+
+template <typename F>
+void with_variant(int v, F &&f) {
+  using I16 = std::integral_constant<int, 16>;
+  using I32 = std::integral_constant<int, 32>;
+  switch (v) {
+    case 0: f(I16{}, std::integral_constant<int, 8>{}); break;
+    case 1: f(I16{}, std::integral_constant<int, 12>{}); break;
+    case 2: f(I16{}, std::integral_constant<int, 15>{}); break;
+    default: f(I32{}, std::integral_constant<int, 24>{}); break;
+  }
+}
 
 struct DevTables {
   int device = -1, p = -1;
@@ -258,10 +275,10 @@ int run_setup_kernels(fmm_mc_ctx *h) {
   hipLaunchKernelGGL(k_stage, dim3(grid_for(h->n, NT)), dim3(NT), 0, st, ch);
   hipLaunchKernelGGL(k_bin_finalize, dim3(grid_for(nleaf, NT)), dim3(NT), 0, st, ch, (int)nleaf);
   const int NG = NT / h->GS;
-  if (h->GS == 16)
-    hipLaunchKernelGGL(k_p2m_leaf<16>, dim3(grid_for(nleaf, NG)), dim3(NT), shm, st, ch, tb, (int)nleaf);
-  else
-    hipLaunchKernelGGL(k_p2m_leaf<32>, dim3(grid_for(nleaf, NG)), dim3(NT), shm, st, ch, tb, (int)nleaf);
+  with_variant(variant_of(h->p), [&](auto gs, auto pm) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m_leaf<decltype(gs)::value, decltype(pm)::value>),
+                       dim3(grid_for(nleaf, NG)), dim3(NT), shm, st, ch, tb, (int)nleaf);
+  });
   for (int l = L - 1; l >= 1; --l)
     hipLaunchKernelGGL(k_m2m, dim3(1 << (3 * (l - 1))), dim3(NT), 0, st, ch, tb, l);
   HIPCHK(hipEventRecord(h->ev1, st));
@@ -269,7 +286,7 @@ int run_setup_kernels(fmm_mc_ctx *h) {
     int n = 1 << (l - 1), half = n / 2;
     int ntgt = half * half * half;
     dim3 grid(grid_for(ntgt, 64), grid_for(h->C, 64), 8);
-    hipLaunchKernelGGL(k_m2l_f64, grid, dim3(NT), 0, st, ch, tb, l);
+    hipLaunchKernelGGL(k_m2l_f64, grid, dim3(M2L_NT), 0, st, ch, tb, l);
   }
   HIPCHK(hipEventRecord(h->ev2, st));
   hipLaunchKernelGGL(k_lattice_init, dim3(1), dim3(NT), 0, st, ch, tb);
@@ -290,10 +307,10 @@ int compute_energy(fmm_mc_ctx *h, double *U) {
   const int NG = NT / h->GS;
   const int nb = grid_for(h->n, NG);
   const size_t shm = (size_t)NG * h->Cs * sizeof(double);
-  if (h->GS == 16)
-    hipLaunchKernelGGL(k_energy<16>, dim3(nb), dim3(NT), shm, h->stream, ch, tb);
-  else
-    hipLaunchKernelGGL(k_energy<32>, dim3(nb), dim3(NT), shm, h->stream, ch, tb);
+  with_variant(variant_of(h->p), [&](auto gs, auto pm) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value>), dim3(nb),
+                       dim3(NT), shm, h->stream, ch, tb);
+  });
   HIPCHK(hipGetLastError());
   std::vector<double> part(nb), K(h->C), H(h->C), dip(3);
   HIPCHK(hipMemcpyAsync(part.data(), ch.red, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -494,12 +511,10 @@ int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
   if (idx < 0 || idx >= h->n) return FMM_MC_ERANGE;
   const Tabs &tb = h->tables->tabs;
   const size_t shm = smem_bytes(h->GS, h->tables->tabs);
-  if (h->GS == 16)
-    hipLaunchKernelGGL(k_propose_one<16>, dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
-                       new_pos[1], new_pos[2]);
-  else
-    hipLaunchKernelGGL(k_propose_one<32>, dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
-                       new_pos[1], new_pos[2]);
+  with_variant(variant_of(h->p), [&](auto gs, auto pm) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_propose_one<decltype(gs)::value, decltype(pm)::value>), dim3(1),
+                       dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0], new_pos[1], new_pos[2]);
+  });
   HIPCHK(hipGetLastError());
   double r[2];
   HIPCHK(hipMemcpyAsync(r, h->ch.scratch, sizeof(r), hipMemcpyDeviceToHost, h->stream));
@@ -524,17 +539,13 @@ int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *
   const size_t shm = smem_bytes(h->GS, h->tables->tabs);
   const int NG = NT / h->GS;
   const int nb = accept_blocks(h->ch.L, NG);
-  if (h->GS == 16) {
-    hipLaunchKernelGGL(k_accept_blocks<16>, dim3(nb), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
-                       new_pos[1], new_pos[2]);
-    hipLaunchKernelGGL(k_accept_book<16>, dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
-                       new_pos[1], new_pos[2], dE);
-  } else {
-    hipLaunchKernelGGL(k_accept_blocks<32>, dim3(nb), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
-                       new_pos[1], new_pos[2]);
-    hipLaunchKernelGGL(k_accept_book<32>, dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0],
-                       new_pos[1], new_pos[2], dE);
-  }
+  with_variant(variant_of(h->p), [&](auto gs, auto pm) {
+    constexpr int G_ = decltype(gs)::value, P_ = decltype(pm)::value;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_blocks<G_, P_>), dim3(nb), dim3(NT), shm, h->stream, h->ch, tb,
+                       idx, new_pos[0], new_pos[1], new_pos[2]);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_book<G_, P_>), dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx,
+                       new_pos[0], new_pos[1], new_pos[2], dE);
+  });
   HIPCHK(hipGetLastError());
   int status = 0;
   HIPCHK(hipMemcpyAsync(&status, h->ch.status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -603,25 +614,27 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
     int G = accept_blocks(h0->ch.L, NG) + 1;  // workgroup 0 proposes, the others update
     int ncu = 0, per = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
-    if (GS == 16)
-      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_run_single<16>, NT, shm));
-    else
-      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_run_single<32>, NT, shm));
+    hipError_t oe = hipSuccess;
+    with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
+      oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, k_run_single<decltype(gs)::value, decltype(pm)::value>, NT, shm);
+    });
+    HIPCHK(oe);
     int cap = std::max(1, ncu * std::max(per, 1));
     G = std::max(1, std::min(G, std::min(cap, ncu)));
     Chain chv = h0->ch;
     void *args[] = {&chv, (void *)&tb, &rp};
-    hipError_t e;
-    if (GS == 16)
-      e = hipLaunchCooperativeKernel((const void *)k_run_single<16>, dim3(G), dim3(NT), args, shm, st);
-    else
-      e = hipLaunchCooperativeKernel((const void *)k_run_single<32>, dim3(G), dim3(NT), args, shm, st);
+    hipError_t e = hipSuccess;
+    with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
+      e = hipLaunchCooperativeKernel((const void *)k_run_single<decltype(gs)::value, decltype(pm)::value>,
+                                     dim3(G), dim3(NT), args, shm, st);
+    });
     if (e != hipSuccess) return FMM_MC_EDEVICE;
   } else {
-    if (GS == 16)
-      hipLaunchKernelGGL(k_run_batched<16>, dim3(n_chains), dim3(NT), shm, st, d_chains, tb, rp);
-    else
-      hipLaunchKernelGGL(k_run_batched<32>, dim3(n_chains), dim3(NT), shm, st, d_chains, tb, rp);
+    with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value>),
+                         dim3(n_chains), dim3(NT), shm, st, d_chains, tb, rp);
+    });
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(h0->ev1, st));

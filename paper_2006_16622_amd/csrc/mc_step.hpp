@@ -107,10 +107,10 @@ struct ProposeOut {
 // the near region together with the matching self term (they cancel). The
 // bin records the bookkeeping of an accept needs are kept in LDS. `spare`
 // is run by the last wavefront while the others evaluate the expansions.
-template <int GS, typename Spare>
+template <int GS, int PM, typename Spare>
 __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS> &sm,
                                  Spare &&spare) {
-  constexpr int NG = NT / GS, PM = PmaxOf<GS>::v;
+  constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   const int Cs = tb.Cs, C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
@@ -280,9 +280,97 @@ __device__ __forceinline__ bool image_in_il(const int s[3], const int c[3], int 
   return mx >= 2;
 }
 
+// One fine-level item (level l >= 4, index in 0..377 over the two
+// interaction lists): the stored target cell it owns and the one or two
+// point contributions (scaled displacement and charge) it adds there.
+struct FineItem {
+  int active;  // 0: the target is owned by the other list's item
+  int two;     // the old-side target also lies in the new list
+  double *dst;
+  double v0[3], v1[3];
+  double q0, q1;
+};
+
+__device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, const Move &mv, int l, int item) {
+  FineItem it;
+  it.active = 0;
+  it.two = 0;
+  const int n = 1 << (l - 1);
+  const double h = ch.a / n;
+  const int side = item / 189, k189 = item % 189;
+  const int *c = side ? mv.c1[l] : mv.c0[l];
+  const int *co = side ? mv.c0[l] : mv.c1[l];
+  const int oc = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
+  const int8_t *o = tb.il_off + (oc * 189 + k189) * 3;
+  int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
+  int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
+  int b_other[3];
+  const bool other = image_in_il(s, co, n, b_other);
+  if (side == 1 && other) return it;  // owned by the old-side item
+  it.active = 1;
+  it.dst = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * tb.Cs;
+  const double *x = side ? mv.rn : mv.r;
+  for (int k = 0; k < 3; ++k) it.v0[k] = (x[k] - (b[k] + 0.5) * h) / h;
+  it.q0 = side ? mv.q : -mv.q;
+  if (side == 0 && other) {
+    it.two = 1;
+    for (int k = 0; k < 3; ++k) it.v1[k] = (mv.rn[k] - (b_other[k] + 0.5) * h) / h;
+    it.q1 = mv.q;
+  }
+  return it;
+}
+
+// Contributions of the move to stored cell s of a coarse level (n = 2 or 4
+// cells per side): bit (27 side + image) of the result is set when image
+// s + n w, w in {-1,0,1}^3, lies in the interaction list of the old (side 0)
+// or new (side 1) cell. Computed by the GS lanes of a group.
 template <int GS>
+__device__ __forceinline__ uint64_t coarse_mask(const Move &mv, int l, const int s[3], int lane) {
+  const int n = 1 << (l - 1);
+  uint64_t m = 0;
+  for (int cand = lane; cand < 54; cand += GS) {
+    const int side = cand / 27, e = cand % 27;
+    const int *c = side ? mv.c1[l] : mv.c0[l];
+    const int w[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
+    int mx = 0;
+    bool valid = true;
+    for (int k = 0; k < 3; ++k) {
+      const int bb = s[k] + n * w[k];
+      const int lo = 2 * (c[k] >> 1) - 2;
+      if (bb < lo || bb >= lo + 6) valid = false;
+      int dd = bb - c[k];
+      dd = dd < 0 ? -dd : dd;
+      mx = dd > mx ? dd : mx;
+    }
+    if (valid && mx >= 2) m |= 1ull << cand;
+  }
+#pragma unroll
+  for (int o = GS / 2; o > 0; o >>= 1) {
+    unsigned lo = (unsigned)m, hi = (unsigned)(m >> 32);
+    lo |= __shfl_xor(lo, o, GS);
+    hi |= __shfl_xor(hi, o, GS);
+    m = (uint64_t)lo | ((uint64_t)hi << 32);
+  }
+  return m;
+}
+
+// add one contribution (candidate bit) of a coarse cell to a group buffer
+template <int GS, int PM>
+__device__ __forceinline__ void coarse_contrib(const Tabs &tb, const double *rec, const Move &mv, int l,
+                                               const int s[3], int cand, double a, int lane, double *buf) {
+  const int n = 1 << (l - 1);
+  const double h = a / n;
+  const int side = cand / 27, e = cand % 27;
+  const int w[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
+  const double *x = side ? mv.rn : mv.r;
+  double v[3];
+  for (int k = 0; k < 3; ++k) v[k] = (x[k] - ((s[k] + n * w[k]) + 0.5) * h) / h;
+  group_harmonics<GS, PM, 2, true>(lane, tb, rec, v[0], v[1], v[2], side ? mv.q : -mv.q, buf);
+}
+
+template <int GS, int PM>
 __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS> &sm) {
-  constexpr int NG = NT / GS, PM = PmaxOf<GS>::v;
+  constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   const int Cs = tb.Cs, C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
@@ -359,44 +447,126 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
   const int l = 4 + b2 / bpl;
   const int item = (b2 % bpl) * NG + g;
   if (l <= L && item < 378) {
-    const int n = 1 << (l - 1);
-    const double h = a / n;
-    int side = item / 189, k189 = item % 189;
-    const int *c = side ? mv.c1[l] : mv.c0[l];
-    const int *co = side ? mv.c0[l] : mv.c1[l];
-    int oc = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
-    const int8_t *o = tb.il_off + (oc * 189 + k189) * 3;
-    int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
-    int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
-    int b_other[3];
-    bool other = image_in_il(s, co, n, b_other);
-    if (side == 1 && other) return;  // owned by the old-side item
+    FineItem it = fine_item(ch, tb, mv, l, item);
+    if (!it.active) return;
     double *buf = acc + (size_t)g * Cs;
-    double *dst = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * Cs;
     // the target's coefficients are loaded while the harmonics are formed
     double old[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       int k = lane + j * GS;
-      old[j] = k < C ? dst[k] : 0.0;
+      old[j] = k < C ? it.dst[k] : 0.0;
     }
-    const double *x = side ? mv.rn : mv.r;
-    double v[3];
-    for (int k = 0; k < 3; ++k) v[k] = (x[k] - (b[k] + 0.5) * h) / h;
-    group_harmonics<GS, PM, 2, false>(lane, tb, sm.rec, v[0], v[1], v[2], side ? q : -q, buf);
-    if (side == 0 && other) {
+    group_harmonics<GS, PM, 2, false>(lane, tb, sm.rec, it.v0[0], it.v0[1], it.v0[2], it.q0, buf);
+    if (it.two) {
       __builtin_amdgcn_wave_barrier();
-      for (int k = 0; k < 3; ++k) v[k] = (mv.rn[k] - (b_other[k] + 0.5) * h) / h;
-      group_harmonics<GS, PM, 2, true>(lane, tb, sm.rec, v[0], v[1], v[2], q, buf);
+      group_harmonics<GS, PM, 2, true>(lane, tb, sm.rec, it.v1[0], it.v1[1], it.v1[2], it.q1, buf);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       int k = lane + j * GS;
-      if (k < C) dst[k] = old[j] + buf[k];
+      if (k < C) it.dst[k] = old[j] + buf[k];
     }
   }
+}
+
+// The whole update of an accepted move by one workgroup (one chain per
+// workgroup): every group works through its own share of targets without
+// workgroup barriers between them. Level 2: each of the 8 stored cells is
+// split over NG/8 groups (partial sums added in a fixed order); level 3: 64
+// stored cells over the groups; levels >= 4: the items of both interaction
+// lists over the groups.
+template <int GS, int PM>
+__device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS> &sm) {
+  constexpr int NG = NT / GS;
+  constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
+  constexpr int SPLIT2 = NG / 8;  // NG is 16 or 8
+  static_assert(NG % 8 == 0, "groups per workgroup");
+  const int Cs = tb.Cs, C = tb.C;
+  const int t = threadIdx.x, g = t / GS, lane = t % GS;
+  const int L = ch.L;
+  const double a = ch.a;
+  double *buf = sm.gbuf + (size_t)g * Cs;
+  // ---- level 2: group g sums part g / 8 of the contributions to cell g % 8
+  {
+    const int cell = g % 8, part = g / 8;
+    const int s3[3] = {cell % 2, (cell / 2) % 2, cell / 4};
+    uint64_t m = coarse_mask<GS>(mv, 2, s3, lane);
+    for (int k = lane; k < Cs; k += GS) buf[k] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    int idx = 0;
+    while (m) {
+      int cand = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      if (idx++ % SPLIT2 == part) coarse_contrib<GS, PM>(tb, sm.rec, mv, 2, s3, cand, a, lane, buf);
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < 8 * C; i += NT) {
+    const int cell = i / C, k = i % C;
+    double sum = 0.0;
+    for (int part = 0; part < SPLIT2; ++part) sum += sm.gbuf[(size_t)(cell + 8 * part) * Cs + k];
+    double *dst = ch.Ld + ch.ld_off[2] + (size_t)cell * Cs;
+    dst[k] += sum;
+  }
+  __syncthreads();
+  // ---- level 3
+  if (L >= 3) {
+    for (int cell = g; cell < 64; cell += NG) {
+      const int s3[3] = {cell % 4, (cell / 4) % 4, cell / 16};
+      double *dst = ch.Ld + ch.ld_off[3] + (size_t)cell * Cs;
+      double old[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        int k = lane + j * GS;
+        old[j] = k < C ? dst[k] : 0.0;
+      }
+      uint64_t m = coarse_mask<GS>(mv, 3, s3, lane);
+      for (int k = lane; k < Cs; k += GS) buf[k] = 0.0;
+      __builtin_amdgcn_wave_barrier();
+      while (m) {
+        int cand = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        coarse_contrib<GS, PM>(tb, sm.rec, mv, 3, s3, cand, a, lane, buf);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        int k = lane + j * GS;
+        if (k < C) dst[k] = old[j] + buf[k];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  // ---- levels >= 4: each item's target is loaded while its harmonics are formed
+  const int nfine = L >= 4 ? (L - 3) * 378 : 0;
+  for (int i = g; i < nfine; i += NG) {
+    FineItem it = fine_item(ch, tb, mv, 4 + i / 378, i % 378);
+    if (!it.active) continue;
+    double old[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      int k = lane + j * GS;
+      old[j] = k < C ? it.dst[k] : 0.0;
+    }
+    group_harmonics<GS, PM, 2, false>(lane, tb, sm.rec, it.v0[0], it.v0[1], it.v0[2], it.q0, buf);
+    if (it.two) {
+      __builtin_amdgcn_wave_barrier();
+      group_harmonics<GS, PM, 2, true>(lane, tb, sm.rec, it.v1[0], it.v1[1], it.v1[2], it.q1, buf);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      int k = lane + j * GS;
+      if (k < C) it.dst[k] = old[j] + buf[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
 }
 
 // Bookkeeping of an accepted move by one workgroup, on the LDS copies of
@@ -404,9 +574,8 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
 // position and leaf bins (the particle to cell map of Sec. 5.2), from the
 // bin records kept in LDS (I_SLOTK, I_CNTOLD, I_CNTNEW, I_IDLAST, stash[0]).
 // Returns nonzero on bin overflow.
-template <int GS>
+template <int GS, int PM>
 __device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &mv, double dE, Lds<GS> &sm) {
-  constexpr int PM = PmaxOf<GS>::v;
   const int C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
   int *ints = sm.ints;

@@ -84,7 +84,7 @@ __device__ __forceinline__ void move_from_draw(const RunParams &rp, const Chain 
   }
 }
 
-template <int GS>
+template <int GS, int PM>
 __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
@@ -92,12 +92,14 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
   __shared__ NextDraw nd;
   __shared__ int s_acc;
   __shared__ double s_u;
+  __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
   const int c = blockIdx.x, t = threadIdx.x;
-  const Chain ch = chains[c];
+  if (t == 0) chl = chains[c];
+  __syncthreads();
+  const Chain &ch = chl;
   Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
   const double D = rp.max_step[c];
-  const int nblk = accept_blocks(ch.L, NG);
   double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
   uint64_t tick_prop = 0, tick_acc = 0;
   int status = 0;
@@ -116,7 +118,7 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
     locate_move_par(ch, mv);
     __syncthreads();
     const double u = s_u;
-    ProposeOut po = propose_wg<GS>(ch, tb, mv, sm, [&](int lane) {
+    ProposeOut po = propose_wg<GS, PM>(ch, tb, mv, sm, [&](int lane) {
       if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
     });
     uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
@@ -142,11 +144,8 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
     prev_idx = mv.idx;
     for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
     if (prev_acc) {
-      for (int b = 0; b < nblk; ++b) {
-        accept_block<GS>(ch, tb, mv, b, sm);
-        __syncthreads();
-      }
-      int ovf = accept_bookkeeping<GS>(ch, tb, mv, po.dE, sm);
+      accept_all_wg<GS, PM>(ch, tb, mv, sm);
+      int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, po.dE, sm);
       if (t == 0) {
         nacc += 1;
         dEsum += po.dE;
@@ -209,15 +208,19 @@ __device__ __forceinline__ bool spin_all_equal(unsigned *flags, int G, unsigned 
 
 constexpr uint64_t SPIN_LIMIT = 100000000ull * 20;  // 20 s of the 100 MHz clock
 
-template <int GS>
-__global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams rp) {
+template <int GS, int PM>
+__global__ void __launch_bounds__(NT) k_run_single(Chain ch_arg, Tabs tb, RunParams rp) {
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
   __shared__ Move mv;
   __shared__ NextDraw nd;
   __shared__ int s_flag, s_acc;
   __shared__ double s_u;
+  __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
   const int t = threadIdx.x, w = blockIdx.x, G = gridDim.x;
+  if (t == 0) chl = ch_arg;
+  __syncthreads();
+  const Chain &ch = chl;
   const int nblk = accept_blocks(ch.L, NG);
   unsigned *seq = ch.sync, *stop = ch.sync + 2, *err = ch.sync + 3, *doneflag = ch.sync + 64;
   double *mb = ch.mbox;
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
       locate_move_par(ch, mv);
       __syncthreads();
       const double u = s_u;
-      ProposeOut po = propose_wg<GS>(ch, tb, mv, sm, [&](int lane) {
+      ProposeOut po = propose_wg<GS, PM>(ch, tb, mv, sm, [&](int lane) {
         if (lane == 0 && step + 1 < rp.steps) draw_into(rp, 0, step + 1, ch, D, nd);
       });
       uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
@@ -285,12 +288,9 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
             st_release(seq, myseq);
           }
         } else {
-          for (int b = 0; b < nblk; ++b) {
-            accept_block<GS>(ch, tb, mv, b, sm);
-            __syncthreads();
-          }
+          accept_all_wg<GS, PM>(ch, tb, mv, sm);
         }
-        int ovf = accept_bookkeeping<GS>(ch, tb, mv, po.dE, sm);
+        int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, po.dE, sm);
         if (t == 0) {
           nacc += 1;
           dEsum += po.dE;
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch, Tabs tb, RunParams 
     locate_move_par(ch, mv);
     __syncthreads();
     for (int b = w - 1; b < nblk; b += G - 1) {
-      accept_block<GS>(ch, tb, mv, b, sm);
+      accept_block<GS, PM>(ch, tb, mv, b, sm);
       __syncthreads();
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -394,7 +394,7 @@ __device__ __forceinline__ void move_direct(const Chain &ch, int64_t idx, double
   __syncthreads();
 }
 
-template <int GS>
+template <int GS, int PM>
 __global__ void __launch_bounds__(NT) k_propose_one(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                     double z) {
   extern __shared__ double lds[];
@@ -402,14 +402,14 @@ __global__ void __launch_bounds__(NT) k_propose_one(Chain ch, Tabs tb, int64_t i
   Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
   move_direct(ch, idx, x, y, z, mv);
-  ProposeOut po = propose_wg<GS>(ch, tb, mv, sm, [](int) {});
+  ProposeOut po = propose_wg<GS, PM>(ch, tb, mv, sm, [](int) {});
   if (threadIdx.x == 0) {
     ch.scratch[0] = po.dE;
     ch.scratch[1] = po.singular;
   }
 }
 
-template <int GS>
+template <int GS, int PM>
 __global__ void __launch_bounds__(NT) k_accept_blocks(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                       double z) {
   extern __shared__ double lds[];
@@ -417,10 +417,10 @@ __global__ void __launch_bounds__(NT) k_accept_blocks(Chain ch, Tabs tb, int64_t
   Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, false);
   move_direct(ch, idx, x, y, z, mv);
-  accept_block<GS>(ch, tb, mv, blockIdx.x, sm);
+  accept_block<GS, PM>(ch, tb, mv, blockIdx.x, sm);
 }
 
-template <int GS>
+template <int GS, int PM>
 __global__ void __launch_bounds__(NT) k_accept_book(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                     double z, double dE) {
   extern __shared__ double lds[];
@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(NT) k_accept_book(Chain ch, Tabs tb, int64_t i
   move_direct(ch, idx, x, y, z, mv);
   load_bin_records(ch, mv, sm);
   __syncthreads();
-  int ovf = accept_bookkeeping<GS>(ch, tb, mv, dE, sm);
+  int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, dE, sm);
   writeback_lds(ch, tb, sm);
   if (threadIdx.x == 0 && ovf) ch.status[0] = -7;
 }

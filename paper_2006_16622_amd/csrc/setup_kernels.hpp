@@ -66,7 +66,7 @@ __global__ void k_bin_finalize(Chain ch, int nleaf) {
 
 // P2M on the leaves, Eq. (multipole_expansion_coefficients), scaled by the
 // leaf size: M^_n^m = sum q (|s|/h)^n Y_n^{-m}
-template <int GS>
+template <int GS, int PM>
 __global__ void k_p2m_leaf(Chain ch, Tabs tb, int nleaf) {
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
@@ -82,7 +82,7 @@ __global__ void k_p2m_leaf(Chain ch, Tabs tb, int nleaf) {
   int cnt = ch.bin_cnt[c];
   for (int j = 0; j < cnt; ++j) {
     double4 pj = ch.bin_p[(size_t)c * ch.B + j];
-    group_harmonics<GS, PmaxOf<GS>::v, 1, true>(lane, tb, tb.rec, (pj.x - (cx + 0.5) * h) / h,
+    group_harmonics<GS, PM, 1, true>(lane, tb, tb.rec, (pj.x - (cx + 0.5) * h) / h,
                                                 (pj.y - (cy + 0.5) * h) / h, (pj.z - (cz + 0.5) * h) / h,
                                                 pj.w, buf);
   }
@@ -116,7 +116,9 @@ __global__ void k_m2m(Chain ch, Tabs tb, int l) {
 // M2L on level l: for each target cell a (octant oc), L^_a = sum over the 189
 // offsets o of IL(oc) of T_o M^_{(a+o) mod n}; a batched GEMM over the target
 // cells of one octant, tiled 64 (outputs) x 64 (cells) x 16 (inputs).
-__global__ void __launch_bounds__(NT) k_m2l_f64(Chain ch, Tabs tb, int l) {
+constexpr int M2L_NT = 256;  // threads of the M2L tile kernel (16 x 16, 4 x 4 outputs each)
+
+__global__ void __launch_bounds__(M2L_NT) k_m2l_f64(Chain ch, Tabs tb, int l) {
   __shared__ double As[16][64 + 1];
   __shared__ double Bs[16][64 + 1];
   __shared__ int src[64];
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(NT) k_m2l_f64(Chain ch, Tabs tb, int l) {
     }
     __syncthreads();
     for (int k0 = 0; k0 < C; k0 += 16) {
-      for (int e = t; e < 16 * 64; e += NT) {
+      for (int e = t; e < 16 * 64; e += M2L_NT) {
         int kk = e / 64, jj = e % 64;
         int k = k0 + kk, j = j0 + jj;
         As[kk][jj] = (k < C && j < C) ? op[(size_t)k * Cs + j] : 0.0;
@@ -211,7 +213,7 @@ __global__ void k_lattice_init(Chain ch, Tabs tb) {
 // per-particle potential phi_i = sum_l Psi^D_l(r_i) + near(r_i) (excluding
 // the particle itself, images included); block partial sums of
 // 1/2 q_i phi_i written to ch.red[block]
-template <int GS>
+template <int GS, int PM>
 __global__ void k_energy(Chain ch, Tabs tb) {
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
@@ -229,7 +231,7 @@ __global__ void k_energy(Chain ch, Tabs tb) {
       double h = a / n;
       int c[3];
       for (int k = 0; k < 3; ++k) c[k] = cell_coord(r[k], ch.inv_h[l], n);
-      group_harmonics<GS, PmaxOf<GS>::v, 0, false>(lane, tb, tb.rec, (r[0] - (c[0] + 0.5) * h) / h,
+      group_harmonics<GS, PM, 0, false>(lane, tb, tb.rec, (r[0] - (c[0] + 0.5) * h) / h,
                                                    (r[1] - (c[1] + 0.5) * h) / h,
                                                    (r[2] - (c[2] + 0.5) * h) / h, 1.0, buf);
       __builtin_amdgcn_wave_barrier();
