@@ -8,7 +8,12 @@
 
 namespace fmmdev {
 
-constexpr int NT = 512;       // threads per workgroup of the Monte Carlo kernels
+// threads per workgroup: the batched run (one workgroup per chain) and the
+// setup kernels use 512; the whole-GPU single chain and the single-call
+// kernels use 256 (shorter barriers on the serial proposal path)
+constexpr int WG_BATCH = 512;
+constexpr int WG_SINGLE = 256;
+constexpr int WG_SETUP = 512;
 constexpr int MAXL = 8;       // levels (depth 7)
 constexpr int NEAR = 27;      // leaf cells of a near region (Alg. 1)
 
@@ -61,7 +66,7 @@ struct Chain {
 // constant tables the step needs (recurrence constants, L2P and bilinear
 // weights, optionally the lattice operator) and the chain's small mutable
 // state (K, H = R(K), dipole, running energy), written back at the end.
-template <int GS>
+template <int GS, int NT>
 struct Lds {
   static constexpr int NG = NT / GS;
   double *rec;                 // 3 Cs: recurrence constants
@@ -273,6 +278,7 @@ __device__ __forceinline__ double group_sum(double v) {
 
 // deterministic workgroup sum of four values at once: shuffle tree inside
 // each wavefront, then the NT/64 wave totals in order; red: 16 doubles of LDS
+template <int NT>
 __device__ __forceinline__ void wg_sum4(double v[4], double *red) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 #pragma unroll
@@ -293,6 +299,7 @@ __device__ __forceinline__ void wg_sum4(double v[4], double *red) {
 }
 
 // deterministic workgroup sum (fixed tree); red: NT doubles of LDS
+template <int NT>
 __device__ __forceinline__ double wg_sum(double v, double *red) {
   int t = threadIdx.x;
   red[t] = v;
@@ -308,7 +315,7 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
 
 // y[s] = sum_k R[s][k] x[k] over the ELL layout of the lattice operator for
 // the output slots s = t, t + NT, ... of the calling thread, handed to `use`
-template <typename F>
+template <int NT, typename F>
 __device__ __forceinline__ void lattice_rows(const Tabs &tb, const double *val, const int *col,
                                              const double *x, F &&use) {
   for (int s = threadIdx.x; s < tb.C; s += NT) {

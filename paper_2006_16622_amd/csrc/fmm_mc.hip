@@ -220,7 +220,7 @@ void make_layout(int64_t n, int levels, int p, Layout &ly) {
   sz[O_SCRATCH] = 8 * 64;
   sz[O_MBOX] = 8 * 64;
   sz[O_SYNC] = 4 * 512;
-  const int NG = NT / group_size(p);
+  const int NG = WG_SETUP / group_size(p);
   sz[O_RED] = 8 * ((n + NG - 1) / NG + 64);
   sz[O_STAGE] = 8 * 4 * n;
   sz[O_STATS] = 8 * 64;
@@ -255,9 +255,11 @@ struct fmm_mc_ctx {
 
 namespace {
 
-size_t smem_bytes(int GS, const Tabs &tb) {
+// dynamic LDS of the Monte Carlo kernels with workgroups of nt threads
+size_t smem_bytes(int GS, const Tabs &tb, int nt) {
   int w = tb.lat_lds ? tb.lat_w : 0;
-  return GS == 16 ? Lds<16>::bytes(tb.Cs, w) : Lds<32>::bytes(tb.Cs, w);
+  if (nt == WG_BATCH) return GS == 16 ? Lds<16, WG_BATCH>::bytes(tb.Cs, w) : Lds<32, WG_BATCH>::bytes(tb.Cs, w);
+  return GS == 16 ? Lds<16, WG_SINGLE>::bytes(tb.Cs, w) : Lds<32, WG_SINGLE>::bytes(tb.Cs, w);
 }
 
 int grid_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
@@ -268,13 +270,14 @@ int run_setup_kernels(fmm_mc_ctx *h) {
   hipStream_t st = h->stream;
   const int L = ch.L;
   const long long nleaf = 1LL << (3 * h->levels);
-  const size_t shm = smem_bytes(h->GS, h->tables->tabs);
+  constexpr int NT = WG_SETUP;
+  const int NG = NT / h->GS;
+  const size_t shm = (size_t)NG * h->Cs * sizeof(double);
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nleaf, NT)), dim3(NT), 0, st, ch.bin_cnt, 0, nleaf);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, ch.status, 0, 8);
   hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(NT), 0, st, (int *)ch.sync, 0, 512);
   hipLaunchKernelGGL(k_stage, dim3(grid_for(h->n, NT)), dim3(NT), 0, st, ch);
   hipLaunchKernelGGL(k_bin_finalize, dim3(grid_for(nleaf, NT)), dim3(NT), 0, st, ch, (int)nleaf);
-  const int NG = NT / h->GS;
   with_variant(variant_of(h->p), [&](auto gs, auto pm) {
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m_leaf<decltype(gs)::value, decltype(pm)::value>),
                        dim3(grid_for(nleaf, NG)), dim3(NT), shm, st, ch, tb, (int)nleaf);
@@ -304,6 +307,7 @@ int run_setup_kernels(fmm_mc_ctx *h) {
 int compute_energy(fmm_mc_ctx *h, double *U) {
   Chain &ch = h->ch;
   const Tabs &tb = h->tables->tabs;
+  constexpr int NT = WG_SETUP;
   const int NG = NT / h->GS;
   const int nb = grid_for(h->n, NG);
   const size_t shm = (size_t)NG * h->Cs * sizeof(double);
@@ -510,10 +514,10 @@ int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
   if (!new_pos || !dE || !finite3(new_pos)) return FMM_MC_EINVAL;
   if (idx < 0 || idx >= h->n) return FMM_MC_ERANGE;
   const Tabs &tb = h->tables->tabs;
-  const size_t shm = smem_bytes(h->GS, h->tables->tabs);
+  const size_t shm = smem_bytes(h->GS, h->tables->tabs, WG_SINGLE);
   with_variant(variant_of(h->p), [&](auto gs, auto pm) {
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_propose_one<decltype(gs)::value, decltype(pm)::value>), dim3(1),
-                       dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0], new_pos[1], new_pos[2]);
+                       dim3(WG_SINGLE), shm, h->stream, h->ch, tb, idx, new_pos[0], new_pos[1], new_pos[2]);
   });
   HIPCHK(hipGetLastError());
   double r[2];
@@ -536,7 +540,8 @@ int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *
     if (rc) return rc;
   }
   const Tabs &tb = h->tables->tabs;
-  const size_t shm = smem_bytes(h->GS, h->tables->tabs);
+  constexpr int NT = WG_SINGLE;
+  const size_t shm = smem_bytes(h->GS, h->tables->tabs, NT);
   const int NG = NT / h->GS;
   const int nb = accept_blocks(h->ch.L, NG);
   with_variant(variant_of(h->p), [&](auto gs, auto pm) {
@@ -568,7 +573,6 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   hipStream_t st = h0->stream;
   const Tabs &tb = h0->tables->tabs;
   const int GS = h0->GS;
-  const size_t shm = smem_bytes(GS, tb);
   // device scratch for per-chain parameters: the first chain's workspace
   // stats area holds max_step (n_chains <= 4096 supported through a
   // temporary allocation otherwise)
@@ -607,6 +611,8 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   rp.tr_leaf = tr_leaf;
   rp.stats = d_stats;
   bool single = (n_chains == 1 && mode != 1);
+  const int NT = single ? WG_SINGLE : WG_BATCH;
+  const size_t shm = smem_bytes(GS, tb, NT);
   if (single) hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 512);
   HIPCHK(hipEventRecord(h0->ev0, st));
   if (single) {

@@ -49,8 +49,8 @@ enum : int {
 
 // Load the constant tables and the chain's small state into LDS (all
 // threads; caller syncs).
-template <int GS>
-__device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<GS> &sm, bool state) {
+template <int GS, int NT>
+__device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<GS, NT> &sm, bool state) {
   const int Cs = tb.Cs;
   for (int i = threadIdx.x; i < 3 * Cs; i += NT) sm.rec[i] = tb.rec[i];
   for (int i = threadIdx.x; i < Cs; i += NT) {
@@ -72,8 +72,8 @@ __device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<G
 }
 
 // write the chain's small state back to global memory (all threads)
-template <int GS>
-__device__ __forceinline__ void writeback_lds(const Chain &ch, const Tabs &tb, Lds<GS> &sm) {
+template <int GS, int NT>
+__device__ __forceinline__ void writeback_lds(const Chain &ch, const Tabs &tb, Lds<GS, NT> &sm) {
   for (int i = threadIdx.x; i < tb.C; i += NT) {
     ch.H[i] = sm.H[i];
     ch.K[i] = sm.K[i];
@@ -82,12 +82,12 @@ __device__ __forceinline__ void writeback_lds(const Chain &ch, const Tabs &tb, L
   if (threadIdx.x == 3) ch.U[0] = sm.st[3];
 }
 
-template <int GS>
-__device__ __forceinline__ const double *lat_val_of(const Tabs &tb, Lds<GS> &sm) {
+template <int GS, int NT>
+__device__ __forceinline__ const double *lat_val_of(const Tabs &tb, Lds<GS, NT> &sm) {
   return tb.lat_lds ? sm.lat_val : tb.lat_val;
 }
-template <int GS>
-__device__ __forceinline__ const int *lat_col_of(const Tabs &tb, Lds<GS> &sm) {
+template <int GS, int NT>
+__device__ __forceinline__ const int *lat_col_of(const Tabs &tb, Lds<GS, NT> &sm) {
   return tb.lat_lds ? sm.lat_col : tb.lat_col;
 }
 
@@ -107,8 +107,8 @@ struct ProposeOut {
 // the near region together with the matching self term (they cancel). The
 // bin records the bookkeeping of an accept needs are kept in LDS. `spare`
 // is run by the last wavefront while the others evaluate the expansions.
-template <int GS, int PM, typename Spare>
-__device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS> &sm,
+template <int GS, int PM, int NT, typename Spare>
+__device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm,
                                  Spare &&spare) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
@@ -223,10 +223,10 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     self = q * q / sqrt(dx * dx + dy * dy + dz * dz);
   }
   double quad = 0.0;
-  lattice_rows(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk,
+  lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk,
                [&](int s, double v) { quad += sm.wdot[s] * sm.dk[s] * v; });
   double part[4] = {dold, dnew, self, quad};
-  wg_sum4(part, sm.red);
+  wg_sum4<NT>(part, sm.red);
   int sing = __syncthreads_or(singular);
 
   ProposeOut out;
@@ -368,8 +368,8 @@ __device__ __forceinline__ void coarse_contrib(const Tabs &tb, const double *rec
   group_harmonics<GS, PM, 2, true>(lane, tb, rec, v[0], v[1], v[2], side ? mv.q : -mv.q, buf);
 }
 
-template <int GS, int PM>
-__device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS> &sm) {
+template <int GS, int PM, int NT>
+__device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS, NT> &sm) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   const int Cs = tb.Cs, C = tb.C;
@@ -478,8 +478,8 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
 // split over NG/8 groups (partial sums added in a fixed order); level 3: 64
 // stored cells over the groups; levels >= 4: the items of both interaction
 // lists over the groups.
-template <int GS, int PM>
-__device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS> &sm) {
+template <int GS, int PM, int NT>
+__device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   constexpr int SPLIT2 = NG / 8;  // NG is 16 or 8
@@ -574,8 +574,8 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
 // position and leaf bins (the particle to cell map of Sec. 5.2), from the
 // bin records kept in LDS (I_SLOTK, I_CNTOLD, I_CNTNEW, I_IDLAST, stash[0]).
 // Returns nonzero on bin overflow.
-template <int GS, int PM>
-__device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &mv, double dE, Lds<GS> &sm) {
+template <int GS, int PM, int NT>
+__device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &mv, double dE, Lds<GS, NT> &sm) {
   const int C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
   int *ints = sm.ints;
@@ -630,7 +630,7 @@ __device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &m
     sm.K[s] += sm.dk[s];
   }
   __syncthreads();
-  lattice_rows(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk, [&](int s, double v) { sm.H[s] += v; });
+  lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk, [&](int s, double v) { sm.H[s] += v; });
   __syncthreads();
   int ovf = ints[I_FLAG];
   __syncthreads();
@@ -639,8 +639,8 @@ __device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &m
 
 // the bin records of the bookkeeping, read from global memory (for an
 // accept that was not preceded by this workgroup's proposal)
-template <int GS>
-__device__ void load_bin_records(const Chain &ch, const Move &mv, Lds<GS> &sm) {
+template <int GS, int NT>
+__device__ void load_bin_records(const Chain &ch, const Move &mv, Lds<GS, NT> &sm) {
   if (threadIdx.x == 0) {
     const int L = ch.L, n = 1 << (L - 1), B = ch.B;
     const int oldc = lin3(n, mv.c0[L][0], mv.c0[L][1], mv.c0[L][2]);

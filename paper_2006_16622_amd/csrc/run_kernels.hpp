@@ -85,7 +85,8 @@ __device__ __forceinline__ void move_from_draw(const RunParams &rp, const Chain 
 }
 
 template <int GS, int PM>
-__global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
+__global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
+  constexpr int NT = WG_BATCH;
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
   __shared__ Move mv;
@@ -97,7 +98,7 @@ __global__ void __launch_bounds__(NT) k_run_batched(const Chain *chains, Tabs tb
   if (t == 0) chl = chains[c];
   __syncthreads();
   const Chain &ch = chl;
-  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
   const double D = rp.max_step[c];
   double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
@@ -209,7 +210,8 @@ __device__ __forceinline__ bool spin_all_equal(unsigned *flags, int G, unsigned 
 constexpr uint64_t SPIN_LIMIT = 100000000ull * 20;  // 20 s of the 100 MHz clock
 
 template <int GS, int PM>
-__global__ void __launch_bounds__(NT) k_run_single(Chain ch_arg, Tabs tb, RunParams rp) {
+__global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb, RunParams rp) {
+  constexpr int NT = WG_SINGLE;
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
   __shared__ Move mv;
@@ -224,7 +226,7 @@ __global__ void __launch_bounds__(NT) k_run_single(Chain ch_arg, Tabs tb, RunPar
   const int nblk = accept_blocks(ch.L, NG);
   unsigned *seq = ch.sync, *stop = ch.sync + 2, *err = ch.sync + 3, *doneflag = ch.sync + 64;
   double *mb = ch.mbox;
-  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, w == 0);
   __syncthreads();
   if (w == 0) {
@@ -395,11 +397,12 @@ __device__ __forceinline__ void move_direct(const Chain &ch, int64_t idx, double
 }
 
 template <int GS, int PM>
-__global__ void __launch_bounds__(NT) k_propose_one(Chain ch, Tabs tb, int64_t idx, double x, double y,
+__global__ void __launch_bounds__(WG_SINGLE) k_propose_one(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                     double z) {
+  constexpr int NT = WG_SINGLE;
   extern __shared__ double lds[];
   __shared__ Move mv;
-  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
   move_direct(ch, idx, x, y, z, mv);
   ProposeOut po = propose_wg<GS, PM>(ch, tb, mv, sm, [](int) {});
@@ -410,22 +413,24 @@ __global__ void __launch_bounds__(NT) k_propose_one(Chain ch, Tabs tb, int64_t i
 }
 
 template <int GS, int PM>
-__global__ void __launch_bounds__(NT) k_accept_blocks(Chain ch, Tabs tb, int64_t idx, double x, double y,
+__global__ void __launch_bounds__(WG_SINGLE) k_accept_blocks(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                       double z) {
+  constexpr int NT = WG_SINGLE;
   extern __shared__ double lds[];
   __shared__ Move mv;
-  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, false);
   move_direct(ch, idx, x, y, z, mv);
   accept_block<GS, PM>(ch, tb, mv, blockIdx.x, sm);
 }
 
 template <int GS, int PM>
-__global__ void __launch_bounds__(NT) k_accept_book(Chain ch, Tabs tb, int64_t idx, double x, double y,
+__global__ void __launch_bounds__(WG_SINGLE) k_accept_book(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                     double z, double dE) {
+  constexpr int NT = WG_SINGLE;
   extern __shared__ double lds[];
   __shared__ Move mv;
-  Lds<GS> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
   move_direct(ch, idx, x, y, z, mv);
   load_bin_records(ch, mv, sm);

@@ -68,7 +68,7 @@ __global__ void k_bin_finalize(Chain ch, int nleaf) {
 // leaf size: M^_n^m = sum q (|s|/h)^n Y_n^{-m}
 template <int GS, int PM>
 __global__ void k_p2m_leaf(Chain ch, Tabs tb, int nleaf) {
-  constexpr int NG = NT / GS;
+  constexpr int NG = WG_SETUP / GS;
   extern __shared__ double lds[];
   const int g = threadIdx.x / GS, lane = threadIdx.x % GS, Cs = tb.Cs;
   double *buf = lds + (size_t)g * Cs;
@@ -99,7 +99,7 @@ __global__ void k_m2m(Chain ch, Tabs tb, int l) {
   int px = pc % n, py = (pc / n) % n, pz = pc / (n * n);
   const double *child = ch.Mp + ch.mp_off[l + 1];
   double *dst = ch.Mp + ch.mp_off[l] + (size_t)pc * Cs;
-  for (int j = threadIdx.x; j < Cs; j += NT) {
+  for (int j = threadIdx.x; j < Cs; j += WG_SETUP) {
     double acc = 0.0;
     if (j < C) {
       for (int oc = 0; oc < 8; ++oc) {
@@ -192,20 +192,20 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l_f64(Chain ch, Tabs tb, int l) {
 // K = level-1 multipole (about the box centre, scaled by a); H = R(K);
 // dipole D = sum q r (one workgroup)
 __global__ void k_lattice_init(Chain ch, Tabs tb) {
-  __shared__ double red[NT];
+  __shared__ double red[WG_SETUP];
   const int C = tb.C, t = threadIdx.x;
   const double *M1 = ch.Mp + ch.mp_off[1];
-  for (int s = t; s < C; s += NT) ch.K[s] = M1[s];
+  for (int s = t; s < C; s += WG_SETUP) ch.K[s] = M1[s];
   __syncthreads();
-  lattice_rows(tb, tb.lat_val, tb.lat_col, M1, [&](int s, double v) { ch.H[s] = v; });
+  lattice_rows<WG_SETUP>(tb, tb.lat_val, tb.lat_col, M1, [&](int s, double v) { ch.H[s] = v; });
   double d[3] = {0, 0, 0};
-  for (int i = t; i < ch.N; i += NT) {
+  for (int i = t; i < ch.N; i += WG_SETUP) {
     d[0] += ch.pq[i] * ch.px[i];
     d[1] += ch.pq[i] * ch.py[i];
     d[2] += ch.pq[i] * ch.pz[i];
   }
   for (int k = 0; k < 3; ++k) {
-    double v = wg_sum(d[k], red);
+    double v = wg_sum<WG_SETUP>(d[k], red);
     if (t == 0) ch.dip[k] = v;
   }
 }
@@ -215,9 +215,9 @@ __global__ void k_lattice_init(Chain ch, Tabs tb) {
 // 1/2 q_i phi_i written to ch.red[block]
 template <int GS, int PM>
 __global__ void k_energy(Chain ch, Tabs tb) {
-  constexpr int NG = NT / GS;
+  constexpr int NG = WG_SETUP / GS;
   extern __shared__ double lds[];
-  __shared__ double red[NT];
+  __shared__ double red[WG_SETUP];
   const int g = threadIdx.x / GS, lane = threadIdx.x % GS, Cs = tb.Cs, C = tb.C;
   double *buf = lds + (size_t)g * Cs;
   int i = blockIdx.x * NG + g;
@@ -262,7 +262,7 @@ __global__ void k_energy(Chain ch, Tabs tb) {
     phi += group_sum<GS>(dn);
     if (lane == 0) contrib = 0.5 * ch.pq[i] * phi;
   }
-  double v = wg_sum(contrib, red);
+  double v = wg_sum<WG_SETUP>(contrib, red);
   if (threadIdx.x == 0) ch.red[blockIdx.x] = v;
 }
 
