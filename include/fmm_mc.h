@@ -76,6 +76,23 @@ int fmm_mc_setup(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_stream,
                  const double *pos, const double *q, double box, int levels, int p,
                  uint32_t flags);
 
+/* Set up n_chains chains of the same degree p in one pass (the batched
+ * form of fmm_mc_setup, for the batched chain loop of fmm_mc_run): every
+ * setup kernel runs once over all chains, and the M2L of every level of
+ * every chain is one launch, because the scaled translation operators do
+ * not depend on the level (Sec. 3.2 initialisation, Sec. 3.4 lattice).
+ * Arrays of length n_chains: dev_ws (device workspaces, each 256-byte
+ * aligned and at least ws_bytes[c] = fmm_mc_workspace_bytes(n[c],
+ * levels[c], p, flags) bytes, owned by the caller), n, pos (host n[c] x 3
+ * AoS), q (host n[c]), box, levels. All chains use hip_stream and the
+ * current device. On success out[c] receives chain c's handle; on failure
+ * no handle is left open and the first error is returned. The library
+ * holds two small stream-ordered device allocations (chain descriptors and
+ * the M2L tile list) for the duration of the call. */
+int fmm_mc_setup_batch(fmm_mc_t *out, int n_chains, void *const *dev_ws, const size_t *ws_bytes,
+                       void *hip_stream, const int64_t *n, const double *const *pos, const double *const *q,
+                       const double *box, const int *levels, int p, uint32_t flags);
+
 /* Energy change of moving charge idx to new_pos (3 doubles, host, absolute;
  * wrapped by the library): Alg. L.1 plus Alg. 1 with the periodic
  * modifications of Sec. 3.4 (self-image correction, far lattice, tin-foil
@@ -153,7 +170,12 @@ int fmm_mc_get_positions(fmm_mc_t h, double *pos);
  * cells ordered x + n (y + n z). */
 int fmm_mc_dump_locals(fmm_mc_t h, int level, double *out);
 
-/* Rebuild every expansion from the current positions (FP64 re-setup). */
+/* Rebuild every expansion from the current (device-resident) positions:
+ * the whole setup pass of fmm_mc_setup, captured into a HIP graph on the
+ * first call (on a private non-blocking stream) and replayed on the
+ * handle's stream afterwards. The running energy is replaced by the fresh
+ * total energy; the setup energy is kept. A bin overflow is reported as
+ * FMM_MC_EOVERFLOW. */
 int fmm_mc_resetup(fmm_mc_t h);
 
 /* Release the handle (not the caller's workspace). */

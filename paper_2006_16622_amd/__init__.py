@@ -8,4 +8,4 @@ arguments (``binding``) and uses PyTorch for device memory and streams.
 There is no CPU fallback: without the built library every call raises.
 """
 from .binding import (FMM_MC_MIXED, FmmMcError, Chain, load_library, run_chains,  # noqa: F401
-                      host_operator, workspace_bytes)
+                      setup_batch, host_operator, workspace_bytes)

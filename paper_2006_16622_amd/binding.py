@@ -53,6 +53,10 @@ SYMBOLS = {
                                               ctypes.POINTER(ctypes.c_size_t)]),
     "fmm_mc_setup": (ctypes.c_int, [ctypes.POINTER(_vp), _vp, ctypes.c_size_t, _vp, ctypes.c_int64, _dp, _dp,
                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_uint32]),
+    "fmm_mc_setup_batch": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
+                                          ctypes.POINTER(ctypes.c_size_t), _vp, _i64p, ctypes.POINTER(_dp),
+                                          ctypes.POINTER(_dp), _dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                          ctypes.c_uint32]),
     "fmm_mc_propose": (ctypes.c_int, [_vp, ctypes.c_int64, _dp, _dp]),
     "fmm_mc_accept": (ctypes.c_int, [_vp, ctypes.c_int64, _dp, _dp, _dp]),
     "fmm_mc_run": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
@@ -114,23 +118,27 @@ class Chain:
     """One Markov chain: positions/charges set up on the GPU (``fmm_mc_setup``)."""
 
     def __init__(self, pos, q, box: float, levels: int, p: int, flags: int = 0, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, _defer: bool = False):
         import torch
         lib = load_library()
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        self._pos, self._q = pos, q
         self.n = len(q)
-        self.levels, self.p, self.box = int(levels), int(p), float(box)
+        self.levels, self.p, self.box, self.flags = int(levels), int(p), float(box), int(flags)
         self.device = torch.device(device)
-        nbytes = workspace_bytes(self.n, self.levels, self.p, flags)
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.nbytes = workspace_bytes(self.n, self.levels, self.p, flags)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
-        aligned = (base + 255) // 256 * 256
+        self.ws_ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._h = _vp()
+        if _defer:
+            return
         with torch.cuda.device(self.device):
-            rc = lib.fmm_mc_setup(ctypes.byref(self._h), _vp(aligned), nbytes, _vp(self.stream.cuda_stream),
-                                  self.n, _d(pos), _d(q), self.box, self.levels, self.p, flags)
+            rc = lib.fmm_mc_setup(ctypes.byref(self._h), _vp(self.ws_ptr), self.nbytes,
+                                  _vp(self.stream.cuda_stream), self.n, _d(pos), _d(q), self.box, self.levels,
+                                  self.p, flags)
         _check(rc, "fmm_mc_setup")
 
     @property
@@ -202,6 +210,31 @@ class Chain:
         out = np.zeros(4)
         _check(load_library().fmm_mc_last_timing(self._h, _d(out), 4), "fmm_mc_last_timing")
         return out
+
+
+def setup_batch(systems, p: int, flags: int = 0, device: str = "cuda:0", stream=None):
+    """fmm_mc_setup_batch over a list of (pos, q, box, levels): one setup
+    pass for all chains. Returns the Chain objects in order."""
+    import torch
+    lib = load_library()
+    chains = [Chain(pos, q, box, levels, p, flags, device, stream, _defer=True)
+              for (pos, q, box, levels) in systems]
+    nc = len(chains)
+    hs = (_vp * nc)()
+    ws = (_vp * nc)(*[c.ws_ptr for c in chains])
+    wb = (ctypes.c_size_t * nc)(*[c.nbytes for c in chains])
+    ns = np.array([c.n for c in chains], dtype=np.int64)
+    pp = (_dp * nc)(*[_d(c._pos) for c in chains])
+    qq = (_dp * nc)(*[_d(c._q) for c in chains])
+    boxes = np.array([c.box for c in chains], dtype=np.float64)
+    lv = (ctypes.c_int * nc)(*[c.levels for c in chains])
+    with torch.cuda.device(chains[0].device):
+        rc = lib.fmm_mc_setup_batch(hs, nc, ws, wb, _vp(chains[0].stream.cuda_stream), ns.ctypes.data_as(_i64p),
+                                    pp, qq, _d(boxes), lv, int(p), int(flags))
+    _check(rc, "fmm_mc_setup_batch")
+    for c, h in zip(chains, hs):
+        c._h = _vp(h)
+    return chains
 
 
 def run_chains(chains, steps: int, seed: int, beta: float, max_step, t0: int = 0, mode: int = 0,

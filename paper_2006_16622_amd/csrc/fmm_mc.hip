@@ -183,7 +183,7 @@ struct Layout {
 
 enum {
   O_PX, O_PY, O_PZ, O_PQ, O_LEAF, O_SLOT, O_BCNT, O_BID, O_BP, O_LD, O_MP, O_K, O_H,
-  O_DIP, O_U, O_STATUS, O_SCRATCH, O_MBOX, O_SYNC, O_RED, O_STAGE, O_STATS, O_CHAIN, O_END
+  O_DIP, O_U, O_STATUS, O_SCRATCH, O_MBOX, O_SYNC, O_RED, O_STAGE, O_STATS, O_CHAIN, O_TILES, O_END
 };
 
 int bin_capacity(int64_t n, int levels) {
@@ -193,6 +193,18 @@ int bin_capacity(int64_t n, int levels) {
   int B = 16;
   while (B < want) B *= 2;
   return B;
+}
+
+// M2L tiles of one chain: per octant, its targets on levels 2..levels+1
+// ((8^levels - 1)/7 of them) in runs of M2L_TT
+long long m2l_octant_targets(int levels) { return ((1LL << (3 * levels)) - 1) / 7; }
+int m2l_tiles(int levels) { return 8 * (int)((m2l_octant_targets(levels) + M2L_TT - 1) / M2L_TT); }
+
+void append_m2l_tiles(std::vector<int4> &out, int chain, int levels) {
+  const long long T = m2l_octant_targets(levels);
+  for (int oc = 0; oc < 8; ++oc)
+    for (long long f = 0; f < T; f += M2L_TT)
+      out.push_back(make_int4(chain, oc, (int)f, (int)std::min<long long>(M2L_TT, T - f)));
 }
 
 void make_layout(int64_t n, int levels, int p, Layout &ly) {
@@ -225,6 +237,7 @@ void make_layout(int64_t n, int levels, int p, Layout &ly) {
   sz[O_STAGE] = 8 * 4 * n;
   sz[O_STATS] = 8 * 64;
   sz[O_CHAIN] = sizeof(Chain);
+  sz[O_TILES] = sizeof(int4) * (size_t)m2l_tiles(levels);
   size_t o = 0;
   for (int i = 0; i < O_END; ++i) {
     ly.off[i] = o;
@@ -249,6 +262,11 @@ struct fmm_mc_ctx {
   Chain *d_chain = nullptr;
   DevTables *tables = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  int4 *d_tiles = nullptr;            // this chain's M2L tile list (workspace)
+  int ntiles = 0;
+  hipStream_t cap_stream = nullptr;   // private stream for graph capture
+  hipGraph_t graph = nullptr;         // captured re-setup
+  hipGraphExec_t gexec = nullptr;
   double last_ms[4] = {0, 0, 0, 0};
   bool ready = false;
 };
@@ -264,77 +282,113 @@ size_t smem_bytes(int GS, const Tabs &tb, int nt) {
 
 int grid_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
 
-int run_setup_kernels(fmm_mc_ctx *h) {
-  Chain &ch = h->ch;
-  const Tabs &tb = h->tables->tabs;
-  hipStream_t st = h->stream;
-  const int L = ch.L;
-  const long long nleaf = 1LL << (3 * h->levels);
+// One setup pass over a batch of chains of the same degree (a single chain
+// is a batch of one): optional restage from the device positions, clear,
+// wrap and bin, P2M, M2M, M2L (all levels and chains in one launch), the
+// lattice moments and the total energy. Only kernels: the sequence can be
+// captured into a graph. e1/e2, if given, bracket the M2L launch.
+struct SetupLaunch {
+  hipStream_t st = nullptr;
+  const Chain *chains = nullptr;  // device array
+  int nchains = 0;
+  long long max_n = 0;
+  int max_levels = 0;
+  const int4 *tiles = nullptr;
+  int ntiles = 0;
+  int p = 0, GS = 16, C = 0, Cs = 0;
+  const Tabs *tb = nullptr;
+  bool restage = false;
+  bool fp32_m2l = false;
+  int energy_mode = 2;
+  hipEvent_t e1 = nullptr, e2 = nullptr;
+};
+
+int enqueue_setup(const SetupLaunch &S) {
+  const Tabs &tb = *S.tb;
+  hipStream_t st = S.st;
   constexpr int NT = WG_SETUP;
-  const int NG = NT / h->GS;
-  const size_t shm = (size_t)NG * h->Cs * sizeof(double);
-  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nleaf, NT)), dim3(NT), 0, st, ch.bin_cnt, 0, nleaf);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NT), 0, st, ch.status, 0, 8);
-  hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(NT), 0, st, (int *)ch.sync, 0, 512);
-  hipLaunchKernelGGL(k_stage, dim3(grid_for(h->n, NT)), dim3(NT), 0, st, ch);
-  hipLaunchKernelGGL(k_bin_finalize, dim3(grid_for(nleaf, NT)), dim3(NT), 0, st, ch, (int)nleaf);
-  with_variant(variant_of(h->p), [&](auto gs, auto pm) {
+  const int NG = NT / S.GS;
+  const int nc = S.nchains;
+  const long long max_nleaf = 1LL << (3 * S.max_levels);
+  const size_t shm = (size_t)NG * S.Cs * sizeof(double);
+  if (S.restage) hipLaunchKernelGGL(k_restage, dim3(grid_for(S.max_n, NT), nc), dim3(NT), 0, st, S.chains);
+  hipLaunchKernelGGL(k_setup_clear, dim3(grid_for(max_nleaf, NT), nc), dim3(NT), 0, st, S.chains);
+  hipLaunchKernelGGL(k_stage, dim3(grid_for(S.max_n, NT), nc), dim3(NT), 0, st, S.chains);
+  hipLaunchKernelGGL(k_bin_finalize, dim3(grid_for(max_nleaf, NT), nc), dim3(NT), 0, st, S.chains);
+  with_variant(variant_of(S.p), [&](auto gs, auto pm) {
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m_leaf<decltype(gs)::value, decltype(pm)::value>),
-                       dim3(grid_for(nleaf, NG)), dim3(NT), shm, st, ch, tb, (int)nleaf);
+                       dim3(grid_for(max_nleaf, NG), nc), dim3(NT), shm, st, S.chains, tb);
   });
-  for (int l = L - 1; l >= 1; --l)
-    hipLaunchKernelGGL(k_m2m, dim3(1 << (3 * (l - 1))), dim3(NT), 0, st, ch, tb, l);
-  HIPCHK(hipEventRecord(h->ev1, st));
-  for (int l = 2; l <= L; ++l) {
-    int n = 1 << (l - 1), half = n / 2;
-    int ntgt = half * half * half;
-    dim3 grid(grid_for(ntgt, 64), grid_for(h->C, 64), 8);
-    hipLaunchKernelGGL(k_m2l_f64, grid, dim3(M2L_NT), 0, st, ch, tb, l);
+  for (int l = S.max_levels; l >= 1; --l)
+    hipLaunchKernelGGL(k_m2m, dim3(1 << (3 * (l - 1)), nc), dim3(256), 0, st, S.chains, tb, l);
+  if (S.e1) HIPCHK(hipEventRecord(S.e1, st));
+  const bool narrow = S.Cs <= 96;
+  const int TO = narrow ? 96 : 192;
+  dim3 mg(S.ntiles, (S.C + TO - 1) / TO);
+  if (S.fp32_m2l) {
+    if (narrow)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<float, 96>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l32);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<float, 192>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l32);
+  } else {
+    if (narrow)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<double, 96>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<double, 192>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l);
   }
-  HIPCHK(hipEventRecord(h->ev2, st));
-  hipLaunchKernelGGL(k_lattice_init, dim3(1), dim3(NT), 0, st, ch, tb);
+  if (S.e2) HIPCHK(hipEventRecord(S.e2, st));
+  hipLaunchKernelGGL(k_lattice_init, dim3(1, nc), dim3(NT), 0, st, S.chains, tb);
+  with_variant(variant_of(S.p), [&](auto gs, auto pm) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value>),
+                       dim3(grid_for(S.max_n, NG), nc), dim3(NT), shm, st, S.chains, tb);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy_final<decltype(gs)::value>), dim3(1, nc), dim3(64), 0, st,
+                       S.chains, tb, S.energy_mode);
+  });
   HIPCHK(hipGetLastError());
-  int status[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(status, ch.status, sizeof(status), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  float ms = 0;
-  HIPCHK(hipEventElapsedTime(&ms, h->ev1, h->ev2));
-  h->last_ms[1] = ms;
-  if (status[1]) return FMM_MC_EOVERFLOW;
   return 0;
 }
 
+SetupLaunch single_launch(fmm_mc_ctx *h) {
+  SetupLaunch S;
+  S.st = h->stream;
+  S.chains = h->d_chain;
+  S.nchains = 1;
+  S.max_n = h->n;
+  S.max_levels = h->levels;
+  S.tiles = h->d_tiles;
+  S.ntiles = h->ntiles;
+  S.p = h->p;
+  S.GS = h->GS;
+  S.C = h->C;
+  S.Cs = h->Cs;
+  S.tb = &h->tables->tabs;
+  S.fp32_m2l = (h->flags & FMM_MC_MIXED) != 0;
+  return S;
+}
+
+// status words of a chain after a setup: overflow of a leaf bin
+int setup_status(fmm_mc_ctx *h) {
+  int status[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(status, h->ch.status, sizeof(status), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return status[1] ? FMM_MC_EOVERFLOW : 0;
+}
+
+// a fresh evaluation of the total energy of the current state
 int compute_energy(fmm_mc_ctx *h, double *U) {
-  Chain &ch = h->ch;
   const Tabs &tb = h->tables->tabs;
   constexpr int NT = WG_SETUP;
   const int NG = NT / h->GS;
-  const int nb = grid_for(h->n, NG);
   const size_t shm = (size_t)NG * h->Cs * sizeof(double);
   with_variant(variant_of(h->p), [&](auto gs, auto pm) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value>), dim3(nb),
-                       dim3(NT), shm, h->stream, ch, tb);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value>),
+                       dim3(grid_for(h->n, NG), 1), dim3(NT), shm, h->stream, h->d_chain, tb);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy_final<decltype(gs)::value>), dim3(1, 1), dim3(64), 0, h->stream,
+                       h->d_chain, tb, 0);
   });
   HIPCHK(hipGetLastError());
-  std::vector<double> part(nb), K(h->C), H(h->C), dip(3);
-  HIPCHK(hipMemcpyAsync(part.data(), ch.red, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpyAsync(K.data(), ch.K, h->C * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpyAsync(H.data(), ch.H, h->C * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpyAsync(dip.data(), ch.dip, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(U, h->ch.scratch + 8, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
-  double u = 0.0;
-  for (double v : part) u += v;
-  // far lattice 1/2 E.H (weighted real form, scaled by 1/a) and the tin-foil term
-  double eh = 0.0;
-  for (int n = 0; n <= h->p; ++n)
-    for (int m = -n; m <= n; ++m) {
-      int s = n * n + n + m;
-      eh += (m == 0 ? 1.0 : 2.0) * K[s] * H[s];
-    }
-  const double a = h->box;
-  u += 0.5 * eh / a;
-  u += -2.0 * M_PI / (3.0 * a * a * a) * (dip[0] * dip[0] + dip[1] * dip[1] + dip[2] * dip[2]);
-  *U = u;
   return 0;
 }
 
@@ -353,8 +407,10 @@ int fmm_mc_workspace_bytes(int64_t n, int levels, int p, uint32_t flags, size_t 
   return FMM_MC_OK;
 }
 
-int fmm_mc_setup(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_stream, int64_t n,
-                 const double *pos, const double *q, double box, int levels, int p, uint32_t flags) {
+// Validate the inputs, carve the workspace, upload the staged charges, the
+// chain descriptor and its M2L tile list; the setup kernels are not run.
+static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_stream, int64_t n,
+                        const double *pos, const double *q, double box, int levels, int p, uint32_t flags) {
   if (!out || !dev_ws || !pos || !q) return FMM_MC_EINVAL;
   if (n < 2 || n > (int64_t)1 << 30 || levels < 1 || levels > LEVELS_MAX || p < 0 || p > PMAX)
     return FMM_MC_EINVAL;
@@ -456,57 +512,132 @@ int fmm_mc_setup(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_stream,
     fmm_mc_destroy(h);
     return FMM_MC_EDEVICE;
   }
-  rc = run_setup_kernels(h);
-  if (rc) {
-    fmm_mc_destroy(h);
-    return rc;
-  }
-  double U = 0.0;
-  rc = compute_energy(h, &U);
-  if (rc) {
-    fmm_mc_destroy(h);
-    return rc;
-  }
-  double u2[2] = {U, U};
-  if (hipMemcpyAsync(ch.U, u2, sizeof(u2), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+  std::vector<int4> tiles;
+  append_m2l_tiles(tiles, 0, levels);
+  h->d_tiles = (int4 *)(w + ly.off[O_TILES]);
+  h->ntiles = (int)tiles.size();
+  if (hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess) {
     fmm_mc_destroy(h);
     return FMM_MC_EDEVICE;
+  }
+  *out = h;
+  return FMM_MC_OK;
+}
+
+int fmm_mc_setup(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_stream, int64_t n,
+                 const double *pos, const double *q, double box, int levels, int p, uint32_t flags) {
+  fmm_mc_t h = nullptr;
+  int rc = create_chain(&h, dev_ws, ws_bytes, hip_stream, n, pos, q, box, levels, p, flags);
+  if (rc) return rc;
+  SetupLaunch S = single_launch(h);
+  S.energy_mode = 2;
+  S.e1 = h->ev1;
+  S.e2 = h->ev2;
+  rc = enqueue_setup(S);
+  if (!rc) rc = setup_status(h);
+  if (!rc) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, h->ev1, h->ev2) == hipSuccess) h->last_ms[1] = ms;
+  }
+  if (rc) {
+    fmm_mc_destroy(h);
+    return rc;
   }
   h->ready = true;
   *out = h;
   return FMM_MC_OK;
 }
 
+int fmm_mc_setup_batch(fmm_mc_t *out, int n_chains, void *const *dev_ws, const size_t *ws_bytes,
+                       void *hip_stream, const int64_t *n, const double *const *pos, const double *const *q,
+                       const double *box, const int *levels, int p, uint32_t flags) {
+  if (!out || n_chains < 1 || !dev_ws || !ws_bytes || !n || !pos || !q || !box || !levels) return FMM_MC_EINVAL;
+  std::vector<fmm_mc_t> hs(n_chains, nullptr);
+  auto fail = [&](int rc) {
+    for (auto *h : hs)
+      if (h) fmm_mc_destroy(h);
+    return rc;
+  };
+  std::vector<Chain> descs(n_chains);
+  std::vector<int4> tiles;
+  long long max_n = 0;
+  int max_levels = 0;
+  for (int c = 0; c < n_chains; ++c) {
+    int rc = create_chain(&hs[c], dev_ws[c], ws_bytes[c], hip_stream, n[c], pos[c], q[c], box[c], levels[c], p,
+                          flags);
+    if (rc) return fail(rc);
+    descs[c] = hs[c]->ch;
+    append_m2l_tiles(tiles, c, levels[c]);
+    max_n = std::max<long long>(max_n, n[c]);
+    max_levels = std::max(max_levels, levels[c]);
+  }
+  fmm_mc_t h0 = hs[0];
+  hipStream_t st = h0->stream;
+  Chain *d_descs = nullptr;
+  int4 *d_tiles = nullptr;
+  if (hipMallocAsync((void **)&d_descs, sizeof(Chain) * n_chains, st) != hipSuccess ||
+      hipMallocAsync((void **)&d_tiles, sizeof(int4) * tiles.size(), st) != hipSuccess)
+    return fail(FMM_MC_EDEVICE);
+  int rc = 0;
+  if (hipMemcpyAsync(d_descs, descs.data(), sizeof(Chain) * n_chains, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    rc = FMM_MC_EDEVICE;
+  if (!rc) {
+    SetupLaunch S = single_launch(h0);
+    S.chains = d_descs;
+    S.nchains = n_chains;
+    S.max_n = max_n;
+    S.max_levels = max_levels;
+    S.tiles = d_tiles;
+    S.ntiles = (int)tiles.size();
+    S.energy_mode = 2;
+    S.e1 = h0->ev1;
+    S.e2 = h0->ev2;
+    rc = enqueue_setup(S);
+  }
+  (void)hipFreeAsync(d_descs, st);
+  (void)hipFreeAsync(d_tiles, st);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = FMM_MC_EDEVICE;
+  for (int c = 0; c < n_chains && !rc; ++c) rc = setup_status(hs[c]);
+  if (rc) return fail(rc);
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, h0->ev1, h0->ev2) == hipSuccess) h0->last_ms[1] = ms;
+  for (int c = 0; c < n_chains; ++c) {
+    hs[c]->ready = true;
+    out[c] = hs[c];
+  }
+  return FMM_MC_OK;
+}
+
+// Re-setup from the device-resident positions: the setup pass, captured
+// once into a graph on a private stream and replayed on the chain's stream.
+// The running energy becomes the fresh total energy; the setup energy stays.
 int fmm_mc_resetup(fmm_mc_t h) {
   if (!h || !h->ready) return FMM_MC_ESTATE;
-  Chain &ch = h->ch;
-  // stage the current positions and charges, then run the full setup again
-  std::vector<double> buf(4 * h->n);
-  HIPCHK(hipMemcpyAsync(buf.data(), ch.px, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpyAsync(buf.data() + h->n, ch.py, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpyAsync(buf.data() + 2 * h->n, ch.pz, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpyAsync(buf.data() + 3 * h->n, ch.pq, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  std::vector<double> stage(4 * h->n);
-  for (int64_t i = 0; i < h->n; ++i) {
-    stage[3 * i] = buf[i];
-    stage[3 * i + 1] = buf[h->n + i];
-    stage[3 * i + 2] = buf[2 * h->n + i];
-    stage[3 * h->n + i] = buf[3 * h->n + i];
+  if (!h->gexec) {
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    SetupLaunch S = single_launch(h);
+    S.st = h->cap_stream;
+    S.restage = true;
+    S.energy_mode = 1;
+    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_setup(S);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc ? rc : FMM_MC_EDEVICE;
+    }
+    h->graph = g;
+    if (hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0) != hipSuccess) {
+      h->gexec = nullptr;
+      return FMM_MC_EDEVICE;
+    }
   }
-  HIPCHK(hipMemcpyAsync(ch.stage, stage.data(), sizeof(double) * 4 * h->n, hipMemcpyHostToDevice, h->stream));
-  double U0[2];
-  HIPCHK(hipMemcpyAsync(U0, ch.U, sizeof(U0), hipMemcpyDeviceToHost, h->stream));
-  int rc = run_setup_kernels(h);
-  if (rc) return rc;
-  double U = 0.0;
-  rc = compute_energy(h, &U);
-  if (rc) return rc;
-  double u2[2] = {U, U0[1]};
-  HIPCHK(hipMemcpyAsync(ch.U, u2, sizeof(u2), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return FMM_MC_OK;
+  HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+  return setup_status(h);
 }
 
 int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
@@ -782,6 +913,9 @@ int fmm_mc_last_timing(fmm_mc_t h, double *out, int nout) {
 
 int fmm_mc_destroy(fmm_mc_t h) {
   if (!h) return FMM_MC_EINVAL;
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   if (h->ev2) (void)hipEventDestroy(h->ev2);

@@ -19,8 +19,37 @@ __global__ void k_fill_f64(double *p, double v, long long n) {
   if (i < n) p[i] = v;
 }
 
+// Every setup kernel serves several chains at once: blockIdx.y is the
+// chain, the chain descriptors are an array in device memory, and blocks
+// beyond a chain's own size return at once. One chain is a batch of one.
+
+// clear the bin counts, the status words and the run's sequence counters
+__global__ void k_setup_clear(const Chain *chains) {
+  const Chain &ch = chains[blockIdx.y];
+  const long long nleaf = 1LL << (3 * ch.d);
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nleaf) ch.bin_cnt[i] = 0;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 8) ch.status[threadIdx.x] = 0;
+    for (int k = threadIdx.x; k < 512; k += blockDim.x) ch.sync[k] = 0u;
+  }
+}
+
+// copy the current positions and charges into the staging area (re-setup
+// from the device-resident state)
+__global__ void k_restage(const Chain *chains) {
+  const Chain &ch = chains[blockIdx.y];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ch.N) return;
+  ch.stage[3 * i + 0] = ch.px[i];
+  ch.stage[3 * i + 1] = ch.py[i];
+  ch.stage[3 * i + 2] = ch.pz[i];
+  ch.stage[3 * ch.N + i] = ch.pq[i];
+}
+
 // wrap positions, locate leaf cells, count bin occupancy
-__global__ void k_stage(Chain ch) {
+__global__ void k_stage(const Chain *chains) {
+  const Chain &ch = chains[blockIdx.y];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ch.N) return;
   double x = wrap_coord(ch.stage[3 * i + 0], ch.a);
@@ -43,7 +72,9 @@ __global__ void k_stage(Chain ch) {
 }
 
 // deterministic bin order (ascending particle id), packed particle records
-__global__ void k_bin_finalize(Chain ch, int nleaf) {
+__global__ void k_bin_finalize(const Chain *chains) {
+  const Chain &ch = chains[blockIdx.y];
+  const int nleaf = 1 << (3 * ch.d);
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nleaf) return;
   int cnt = ch.bin_cnt[c];
@@ -65,11 +96,13 @@ __global__ void k_bin_finalize(Chain ch, int nleaf) {
 }
 
 // P2M on the leaves, Eq. (multipole_expansion_coefficients), scaled by the
-// leaf size: M^_n^m = sum q (|s|/h)^n Y_n^{-m}
+// leaf size: M^_n^m = sum q (|s|/h)^n Y_n^{-m}; one lane group per leaf
 template <int GS, int PM>
-__global__ void k_p2m_leaf(Chain ch, Tabs tb, int nleaf) {
+__global__ void k_p2m_leaf(const Chain *chains, Tabs tb) {
   constexpr int NG = WG_SETUP / GS;
   extern __shared__ double lds[];
+  const Chain &ch = chains[blockIdx.y];
+  const int nleaf = 1 << (3 * ch.d);
   const int g = threadIdx.x / GS, lane = threadIdx.x % GS, Cs = tb.Cs;
   double *buf = lds + (size_t)g * Cs;
   int c = blockIdx.x * NG + g;
@@ -83,8 +116,7 @@ __global__ void k_p2m_leaf(Chain ch, Tabs tb, int nleaf) {
   for (int j = 0; j < cnt; ++j) {
     double4 pj = ch.bin_p[(size_t)c * ch.B + j];
     group_harmonics<GS, PM, 1, true>(lane, tb, tb.rec, (pj.x - (cx + 0.5) * h) / h,
-                                                (pj.y - (cy + 0.5) * h) / h, (pj.z - (cz + 0.5) * h) / h,
-                                                pj.w, buf);
+                                     (pj.y - (cy + 0.5) * h) / h, (pj.z - (cz + 0.5) * h) / h, pj.w, buf);
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -92,14 +124,18 @@ __global__ void k_p2m_leaf(Chain ch, Tabs tb, int nleaf) {
   for (int s = lane; s < Cs; s += GS) dst[s] = buf[s];
 }
 
-// M2M from level l+1 to level l (one workgroup per parent cell)
-__global__ void k_m2m(Chain ch, Tabs tb, int l) {
+// M2M from level l+1 to level l (one workgroup per parent cell); chains
+// whose finest level is l or coarser take no part
+__global__ void k_m2m(const Chain *chains, Tabs tb, int l) {
+  const Chain &ch = chains[blockIdx.y];
+  if (l >= ch.L) return;
   const int n = 1 << (l - 1), nc = 2 * n, C = tb.C, Cs = tb.Cs;
   int pc = blockIdx.x;
+  if (pc >= n * n * n) return;
   int px = pc % n, py = (pc / n) % n, pz = pc / (n * n);
   const double *child = ch.Mp + ch.mp_off[l + 1];
   double *dst = ch.Mp + ch.mp_off[l] + (size_t)pc * Cs;
-  for (int j = threadIdx.x; j < Cs; j += WG_SETUP) {
+  for (int j = threadIdx.x; j < Cs; j += blockDim.x) {
     double acc = 0.0;
     if (j < C) {
       for (int oc = 0; oc < 8; ++oc) {
@@ -113,85 +149,167 @@ __global__ void k_m2m(Chain ch, Tabs tb, int l) {
   }
 }
 
-// M2L on level l: for each target cell a (octant oc), L^_a = sum over the 189
-// offsets o of IL(oc) of T_o M^_{(a+o) mod n}; a batched GEMM over the target
-// cells of one octant, tiled 64 (outputs) x 64 (cells) x 16 (inputs).
-constexpr int M2L_NT = 256;  // threads of the M2L tile kernel (16 x 16, 4 x 4 outputs each)
-
-__global__ void __launch_bounds__(M2L_NT) k_m2l_f64(Chain ch, Tabs tb, int l) {
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
-  __shared__ int src[64];
-  const int n = 1 << (l - 1), half = n >> 1 ? n >> 1 : 1;
-  const int C = tb.C, Cs = tb.Cs;
-  const int oc = blockIdx.z, j0 = blockIdx.y * 64, p0 = blockIdx.x * 64;
-  const int ntgt = half * half * half;
-  const int t = threadIdx.x, tj = t % 16, tc = t / 16;
-  const int ox = oc & 1, oy = (oc >> 1) & 1, oz = (oc >> 2) & 1;
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc[i][k] = 0.0;
-  const double *M = ch.Mp + ch.mp_off[l];
-  for (int k189 = 0; k189 < 189; ++k189) {
-    const int8_t *o = tb.il_off + (oc * 189 + k189) * 3;
-    const double *op = tb.m2l + (size_t)tb.il_id[oc * 189 + k189] * C * Cs;
-    __syncthreads();
-    if (t < 64) {
-      int pl = p0 + t;
-      int s = -1;
-      if (pl < ntgt) {
-        int Px = pl % half, Py = (pl / half) % half, Pz = pl / (half * half);
-        int ax = 2 * Px + ox + o[0], ay = 2 * Py + oy + o[1], az = 2 * Pz + oz + o[2];
-        s = lin3(n, imod(ax, n), imod(ay, n), imod(az, n));
-      }
-      src[t] = s;
-    }
-    __syncthreads();
-    for (int k0 = 0; k0 < C; k0 += 16) {
-      for (int e = t; e < 16 * 64; e += M2L_NT) {
-        int kk = e / 64, jj = e % 64;
-        int k = k0 + kk, j = j0 + jj;
-        As[kk][jj] = (k < C && j < C) ? op[(size_t)k * Cs + j] : 0.0;
-        int cc = e / 16, k2 = e % 16;
-        int s = src[cc];
-        Bs[k2][cc] = (s >= 0 && k0 + k2 < C) ? M[(size_t)s * Cs + k0 + k2] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = As[kk][tj + 16 * i];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) bv[i] = Bs[kk][tc + 16 * i];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) acc[i][k] += av[i] * bv[k];
-      }
-      __syncthreads();
-    }
+// ------------------------------------------------------------------ M2L
+// L^_a = sum over the 189 offsets o of IL(octant of a) of T_o M^_{(a+o) mod n}
+// (the FMM initialisation without L2L, Sec. 3.2). The operators T_o do not
+// depend on the level (coefficients are scaled by the cell size), so every
+// target cell of one octant, on any level of any chain, multiplies the same
+// 189 matrices: a batched GEMM on the matrix cores. A tile is up to 64
+// targets of one octant of one chain; a workgroup computes TO output
+// coefficients of its tile. The four wavefronts each own 6 x 2 (TO = 192)
+// or 3 x 2 (TO = 96) 16 x 16 accumulator blocks; inputs are staged through
+// LDS in chunks of 16, double-buffered, the multipoles gathered per target.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  double *Ld = ch.Ld + ch.ld_off[l];
+  // row within the 16 x 16 block of accumulator element v of lane `lane`
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+constexpr int M2L_NT = 256;  // threads of the M2L kernel
+constexpr int M2L_TT = 64;   // targets per tile
+constexpr int M2L_KC = 16;   // inputs per staged chunk
+
+// target t of an octant's list (levels 2, 3, ... in turn, 8^(l-2) targets
+// on level l, each level's targets in x-fastest order): its level and cell
+__device__ __forceinline__ int m2l_target(int t, int oc, int c[3]) {
+  int l = 2, base = 0, cnt = 1;
+  while (t >= base + cnt) {
+    base += cnt;
+    cnt <<= 3;
+    ++l;
+  }
+  const int i = t - base, sh = l - 2, half = 1 << sh;
+  c[0] = 2 * (i & (half - 1)) + (oc & 1);
+  c[1] = 2 * ((i >> sh) & (half - 1)) + ((oc >> 1) & 1);
+  c[2] = 2 * (i >> (2 * sh)) + (oc >> 2);
+  return l;
+}
+
+template <typename T, int TO>
+__global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, const int4 *tiles, const T *ops) {
+  using MF = Mfma<T>;
+  constexpr int RB = TO / 32;  // row blocks of a wavefront
+  __shared__ T As[2][M2L_KC][TO];
+  __shared__ T Bs[2][M2L_KC][M2L_TT];
+  const int4 tl = tiles[blockIdx.x];
+  const Chain &ch = chains[tl.x];
+  const int oc = tl.y, first = tl.z, count = tl.w;
+  const int j0 = blockIdx.y * TO;
+  const int C = tb.C, Cs = tb.Cs;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int ro = (w >> 1) * (TO / 2), co = (w & 1) * 32;
+  // loader roles: A rows t/16 of the chunk, 4 outputs at (t%16)*4 + 64 r;
+  // B target t%64, inputs (t/64)*4 .. +3 of the chunk
+  const int arow = t >> 4, acol = (t & 15) * 4;
+  const int bt = t & 63, brow = (t >> 6) * 4;
+  const bool bvalid = bt < count;
+  int bc[3] = {0, 0, 0}, bn = 1;
+  const double *bsrc = nullptr;
+  if (bvalid) {
+    const int l = m2l_target(first + bt, oc, bc);
+    bn = 1 << (l - 1);
+    bsrc = ch.Mp + ch.mp_off[l];
+  }
+  constexpr int AR = (TO + 63) / 64;
+  const int nq = (C + M2L_KC - 1) / M2L_KC;
+  const int total = 189 * nq;
+  T ra[AR][4], rb[4];
+  auto fetch = [&](int it) {
+    const int k = it / nq, s0 = (it - k * nq) * M2L_KC;
+    const int id = tb.il_id[oc * 189 + k];
+    const int s = s0 + arow;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int pl = p0 + tc + 16 * k;
-    if (pl >= ntgt) continue;
-    int Px = pl % half, Py = (pl / half) % half, Pz = pl / (half * half);
-    int cell = lin3(n, 2 * Px + ox, 2 * Py + oy, 2 * Pz + oz);
+    for (int r = 0; r < AR; ++r) {
+      const int col = acol + 64 * r;
+      const bool ok = s < C && col < TO && j0 + col < Cs;
+      const T *pa = ops + ((size_t)id * C + (ok ? s : 0)) * Cs + j0 + (ok ? col : 0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int j = j0 + tj + 16 * i;
-      if (j < C) Ld[(size_t)cell * Cs + j] = acc[i][k];
+      for (int e = 0; e < 4; ++e) ra[r][e] = ok ? pa[e] : (T)0;
     }
+    if (bvalid) {
+      const int8_t *o = tb.il_off + (oc * 189 + k) * 3;
+      const int x = imod(bc[0] + o[0], bn), y = imod(bc[1] + o[1], bn), z = imod(bc[2] + o[2], bn);
+      const double *pb = bsrc + (size_t)lin3(bn, x, y, z) * Cs + s0 + brow;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rb[e] = (T)pb[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rb[e] = (T)0;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < AR; ++r) {
+      const int col = acol + 64 * r;
+      if (col < TO)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[buf][arow][col + e] = ra[r][e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Bs[buf][brow + e][bt] = rb[e];
+  };
+  typename MF::acc_t acc[RB][2];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (typename MF::acc_t){0, 0, 0, 0};
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int it = 0; it < total; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < total) fetch(it + 1);
+#pragma unroll
+    for (int k4 = 0; k4 < M2L_KC; k4 += 4) {
+      const int kr = k4 + (lane >> 4);
+      const T b0 = Bs[buf][kr][co + (lane & 15)], b1 = Bs[buf][kr][co + 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const T a = As[buf][kr][ro + 16 * i + (lane & 15)];
+        acc[i][0] = MF::mma(a, b0, acc[i][0]);
+        acc[i][1] = MF::mma(a, b1, acc[i][1]);
+      }
+    }
+    if (it + 1 < total) stash(buf ^ 1);
+    __syncthreads();
+  }
+  // store: lane holds, per block, target co + 16 j + lane%16 and rows MF::row
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int tt = co + 16 * j + (lane & 15);
+    if (tt >= count) continue;
+    int c[3];
+    const int l = m2l_target(first + tt, oc, c);
+    const int n = 1 << (l - 1);
+    double *dst = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = j0 + ro + 16 * i + MF::row(lane, v);
+        if (r < Cs) dst[r] = (double)acc[i][j][v];
+      }
   }
 }
 
 // K = level-1 multipole (about the box centre, scaled by a); H = R(K);
-// dipole D = sum q r (one workgroup)
-__global__ void k_lattice_init(Chain ch, Tabs tb) {
+// dipole D = sum q r (one workgroup per chain)
+__global__ void k_lattice_init(const Chain *chains, Tabs tb) {
+  const Chain &ch = chains[blockIdx.y];
   __shared__ double red[WG_SETUP];
   const int C = tb.C, t = threadIdx.x;
   const double *M1 = ch.Mp + ch.mp_off[1];
@@ -214,10 +332,12 @@ __global__ void k_lattice_init(Chain ch, Tabs tb) {
 // the particle itself, images included); block partial sums of
 // 1/2 q_i phi_i written to ch.red[block]
 template <int GS, int PM>
-__global__ void k_energy(Chain ch, Tabs tb) {
+__global__ void k_energy(const Chain *chains, Tabs tb) {
   constexpr int NG = WG_SETUP / GS;
   extern __shared__ double lds[];
   __shared__ double red[WG_SETUP];
+  const Chain &ch = chains[blockIdx.y];
+  if ((long long)blockIdx.x * NG >= ch.N) return;
   const int g = threadIdx.x / GS, lane = threadIdx.x % GS, Cs = tb.Cs, C = tb.C;
   double *buf = lds + (size_t)g * Cs;
   int i = blockIdx.x * NG + g;
@@ -264,6 +384,30 @@ __global__ void k_energy(Chain ch, Tabs tb) {
   }
   double v = wg_sum<WG_SETUP>(contrib, red);
   if (threadIdx.x == 0) ch.red[blockIdx.x] = v;
+}
+
+// total energy: the block partials of k_energy in order, the far lattice
+// 1/2 E.H (real weighted form, scaled by 1/a) and the tin-foil term
+// -(2 pi / 3V) |D|^2 (Sec. 3.4). The result goes to scratch[8]; mode 1 also
+// sets the running energy, mode 2 both the running and the setup energy.
+template <int GS>
+__global__ void k_energy_final(const Chain *chains, Tabs tb, int mode) {
+#pragma clang fp contract(off)
+  const Chain &ch = chains[blockIdx.y];
+  if (threadIdx.x != 0) return;
+  constexpr int NG = WG_SETUP / GS;
+  const int nb = (ch.N + NG - 1) / NG;
+  double u = 0.0;
+  for (int b = 0; b < nb; ++b) u += ch.red[b];
+  double eh = 0.0;
+  for (int s = 0; s < tb.C; ++s) eh += tb.wdot[s] * ch.K[s] * ch.H[s];
+  const double a = ch.a;
+  u += 0.5 * eh / a;
+  const double d2 = ch.dip[0] * ch.dip[0] + ch.dip[1] * ch.dip[1] + ch.dip[2] * ch.dip[2];
+  u += -2.0 * M_PI / (3.0 * a * a * a) * d2;
+  ch.scratch[8] = u;
+  if (mode >= 1) ch.U[0] = u;
+  if (mode >= 2) ch.U[1] = u;
 }
 
 }  // namespace fmmdev
