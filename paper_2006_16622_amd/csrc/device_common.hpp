@@ -70,6 +70,7 @@ template <int GS, int NT>
 struct Lds {
   static constexpr int NG = NT / GS;
   double *rec;                 // 3 Cs: recurrence constants
+  float *rec32;                // 3 Cs: the same in FP32 (mixed precision evaluation)
   double *wl2p, *wdot, *sgnc;  // Cs each
   double *H, *K;               // Cs each: chain state
   double *st;                  // 8: dipole[3], running energy, setup energy
@@ -99,9 +100,19 @@ struct Lds {
     stash = (double4 *)(vals + 32);
     ints = (int *)(stash + 2);
     lat_col = ints + 384;
+    rec32 = (float *)(lat_col + (size_t)ellw * Cs);
   }
   static size_t bytes(int Cs, int ellw) {
-    return sizeof(double) * ((size_t)(NG + 12 + ellw) * Cs + 8 + NT + 32 + 8) + 4 * (384 + (size_t)ellw * Cs);
+    return sizeof(double) * ((size_t)(NG + 12 + ellw) * Cs + 8 + NT + 32 + 8) + 4 * (384 + (size_t)ellw * Cs) +
+           4 * 3 * (size_t)Cs;
+  }
+  // recurrence constants in the evaluation type
+  template <typename R>
+  __device__ const R *rec_of() const {
+    if constexpr (sizeof(R) == 4)
+      return rec32;
+    else
+      return rec;
   }
 };
 
@@ -202,67 +213,83 @@ __device__ __forceinline__ double shift_up(double v) {
 }
 
 template <int GS, int O>
-__device__ __forceinline__ void scan_step(int lane, double &wr, double &wi, double &s, bool irregular) {
+__device__ __forceinline__ float shift_up(float v) {
+  if constexpr (GS == 16) {
+    int b = __float_as_int(v);
+    b = __builtin_amdgcn_update_dpp(b, b, 0x110 + O, 0xf, 0xf, false);
+    return __int_as_float(b);
+  } else {
+    return __shfl_up(v, O, GS);
+  }
+}
+
+template <int GS, int O, typename R>
+__device__ __forceinline__ void scan_step(int lane, R &wr, R &wi, R &s, bool irregular) {
   if constexpr (O < GS) {
-    double ur = shift_up<GS, O>(wr), ui = shift_up<GS, O>(wi);
-    double us = irregular ? shift_up<GS, O>(s) : 1.0;
+    R ur = shift_up<GS, O>(wr), ui = shift_up<GS, O>(wi);
+    R us = irregular ? shift_up<GS, O>(s) : R(1);
     if (lane >= O) {
-      double nr = wr * ur - wi * ui;
-      double ni = wr * ui + wi * ur;
+      R nr = wr * ur - wi * ui;
+      R ni = wr * ui + wi * ur;
       wr = nr;
       wi = ni;
       if (irregular) s *= us;
     }
-    scan_step<GS, 2 * O>(lane, wr, wi, s, irregular);
+    scan_step<GS, 2 * O, R>(lane, wr, wi, s, irregular);
   }
 }
 
-template <int GS, int PMAX, int KIND, bool ACC>
-__device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const double *rec, double x,
-                                                double y, double z, double c, double *buf) {
+__device__ __forceinline__ double sqrt_r(double v) { return sqrt(v); }
+__device__ __forceinline__ float sqrt_r(float v) { return sqrtf(v); }
+
+// R is the arithmetic type of the evaluation (double, or float in the mixed
+// precision mode); the results are stored as doubles.
+template <int GS, int PMAX, int KIND, bool ACC, typename R = double>
+__device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const R *rec, R x, R y, R z, R c,
+                                                double *buf) {
   const int p = tb.p, Cs = tb.Cs;
   const int m = lane;
-  const double r2 = x * x + y * y + z * z;
+  const R r2 = x * x + y * y + z * z;
   // (x + i y)^m and, for KIND 2, |x|^-(2m+1), by a multiplicative scan over the lanes
-  double wr = m == 0 ? 1.0 : x, wi = m == 0 ? 0.0 : y;
-  double inv_r2 = 0.0, s = 1.0;
+  R wr = m == 0 ? R(1) : x, wi = m == 0 ? R(0) : y;
+  R inv_r2 = R(0), s = R(1);
   if (KIND == 2) {
-    inv_r2 = 1.0 / r2;
-    s = m == 0 ? sqrt(inv_r2) : inv_r2;
+    inv_r2 = R(1) / r2;
+    s = m == 0 ? sqrt_r(inv_r2) : inv_r2;
   }
-  scan_step<GS, 1>(lane, wr, wi, s, KIND == 2);
+  scan_step<GS, 1, R>(lane, wr, wi, s, KIND == 2);
   if (m > p) return;
-  const double cm = rec[2 * Cs + m];
-  double tr = wr * cm, ti = wi * cm;
-  double pr = 0.0, pi = 0.0;  // T_{n-2}
-  const double im_sign = (KIND == 0) ? 1.0 : -1.0;
+  const R cm = rec[2 * Cs + m];
+  R tr = wr * cm, ti = wi * cm;
+  R pr = R(0), pi = R(0);  // T_{n-2}
+  const R im_sign = (KIND == 0) ? R(1) : R(-1);
 #pragma unroll
   for (int j = 0; j <= PMAX; ++j) {
     const int n = m + j;
     if (n <= p) {
       if (j > 0) {
         const int sl = n * n + n + m;
-        double a = rec[sl] * z, b = rec[Cs + sl] * r2;
-        double nr = a * tr - b * pr;
-        double ni = a * ti - b * pi;
+        R a = rec[sl] * z, b = rec[Cs + sl] * r2;
+        R nr = a * tr - b * pr;
+        R ni = a * ti - b * pi;
         pr = tr;
         pi = ti;
         tr = nr;
         ti = ni;
         if (KIND == 2) s *= inv_r2;
       }
-      const double f = c * s;
+      const R f = c * s;
       const int sp = n * n + n + m;
       if (ACC)
-        buf[sp] += f * tr;
+        buf[sp] += (double)(f * tr);
       else
-        buf[sp] = f * tr;
+        buf[sp] = (double)(f * tr);
       if (m > 0) {
         const int sn = n * n + n - m;
         if (ACC)
-          buf[sn] += im_sign * f * ti;
+          buf[sn] += (double)(im_sign * f * ti);
         else
-          buf[sn] = im_sign * f * ti;
+          buf[sn] = (double)(im_sign * f * ti);
       }
     }
   }

@@ -45,6 +45,23 @@ void with_variant(int v, F &&f) {
   }
 }
 
+template <class T>
+struct TypeTag {
+  using type = T;
+};
+
+// run-kernel variants: the lane-group variant of p and the evaluation type
+// (FP32 in the mixed-precision mode)
+template <typename F>
+void with_run_variant(int p, bool mixed, F &&f) {
+  with_variant(variant_of(p), [&](auto gs, auto pm) {
+    if (mixed)
+      f(gs, pm, TypeTag<float>{});
+    else
+      f(gs, pm, TypeTag<double>{});
+  });
+}
+
 struct DevTables {
   int device = -1, p = -1;
   Tabs tabs{};
@@ -646,8 +663,9 @@ int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
   if (idx < 0 || idx >= h->n) return FMM_MC_ERANGE;
   const Tabs &tb = h->tables->tabs;
   const size_t shm = smem_bytes(h->GS, h->tables->tabs, WG_SINGLE);
-  with_variant(variant_of(h->p), [&](auto gs, auto pm) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_propose_one<decltype(gs)::value, decltype(pm)::value>), dim3(1),
+  with_run_variant(h->p, h->flags & FMM_MC_MIXED, [&](auto gs, auto pm, auto rt) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_propose_one<decltype(gs)::value, decltype(pm)::value,
+                                                     typename decltype(rt)::type>), dim3(1),
                        dim3(WG_SINGLE), shm, h->stream, h->ch, tb, idx, new_pos[0], new_pos[1], new_pos[2]);
   });
   HIPCHK(hipGetLastError());
@@ -675,9 +693,10 @@ int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *
   const size_t shm = smem_bytes(h->GS, h->tables->tabs, NT);
   const int NG = NT / h->GS;
   const int nb = accept_blocks(h->ch.L, NG);
-  with_variant(variant_of(h->p), [&](auto gs, auto pm) {
+  with_run_variant(h->p, h->flags & FMM_MC_MIXED, [&](auto gs, auto pm, auto rt) {
     constexpr int G_ = decltype(gs)::value, P_ = decltype(pm)::value;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_blocks<G_, P_>), dim3(nb), dim3(NT), shm, h->stream, h->ch, tb,
+    using R_ = typename decltype(rt)::type;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_blocks<G_, P_, R_>), dim3(nb), dim3(NT), shm, h->stream, h->ch, tb,
                        idx, new_pos[0], new_pos[1], new_pos[2]);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_book<G_, P_>), dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx,
                        new_pos[0], new_pos[1], new_pos[2], dE);
@@ -698,9 +717,11 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   fmm_mc_t h0 = chains[0];
   for (int c = 0; c < n_chains; ++c) {
     if (!chains[c] || !chains[c]->ready) return FMM_MC_ESTATE;
-    if (chains[c]->p != h0->p || chains[c]->device != h0->device || chains[c]->stream != h0->stream)
+    if (chains[c]->p != h0->p || chains[c]->device != h0->device || chains[c]->stream != h0->stream ||
+        ((chains[c]->flags ^ h0->flags) & FMM_MC_MIXED))
       return FMM_MC_ESTATE;
   }
+  const bool mixed = (h0->flags & FMM_MC_MIXED) != 0;
   hipStream_t st = h0->stream;
   const Tabs &tb = h0->tables->tabs;
   const int GS = h0->GS;
@@ -752,9 +773,9 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
     int ncu = 0, per = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
     hipError_t oe = hipSuccess;
-    with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
+    with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
       oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, k_run_single<decltype(gs)::value, decltype(pm)::value>, NT, shm);
+          &per, k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>, NT, shm);
     });
     HIPCHK(oe);
     int cap = std::max(1, ncu * std::max(per, 1));
@@ -762,14 +783,16 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
     Chain chv = h0->ch;
     void *args[] = {&chv, (void *)&tb, &rp};
     hipError_t e = hipSuccess;
-    with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
-      e = hipLaunchCooperativeKernel((const void *)k_run_single<decltype(gs)::value, decltype(pm)::value>,
-                                     dim3(G), dim3(NT), args, shm, st);
+    with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
+      e = hipLaunchCooperativeKernel(
+          (const void *)k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>,
+          dim3(G), dim3(NT), args, shm, st);
     });
     if (e != hipSuccess) return FMM_MC_EDEVICE;
   } else {
-    with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value>),
+    with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value,
+                                                       typename decltype(rt)::type>),
                          dim3(n_chains), dim3(NT), shm, st, d_chains, tb, rp);
     });
   }

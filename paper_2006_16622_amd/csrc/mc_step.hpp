@@ -52,7 +52,10 @@ enum : int {
 template <int GS, int NT>
 __device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<GS, NT> &sm, bool state) {
   const int Cs = tb.Cs;
-  for (int i = threadIdx.x; i < 3 * Cs; i += NT) sm.rec[i] = tb.rec[i];
+  for (int i = threadIdx.x; i < 3 * Cs; i += NT) {
+    sm.rec[i] = tb.rec[i];
+    sm.rec32[i] = (float)tb.rec[i];
+  }
   for (int i = threadIdx.x; i < Cs; i += NT) {
     sm.wl2p[i] = tb.wl2p[i];
     sm.wdot[i] = tb.wdot[i];
@@ -107,7 +110,7 @@ struct ProposeOut {
 // the near region together with the matching self term (they cancel). The
 // bin records the bookkeeping of an accept needs are kept in LDS. `spare`
 // is run by the last wavefront while the others evaluate the expansions.
-template <int GS, int PM, int NT, typename Spare>
+template <int GS, int PM, typename R, int NT, typename Spare>
 __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm,
                                  Spare &&spare) {
   constexpr int NG = NT / GS;
@@ -158,7 +161,11 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
       double dx = x[0] - (pj.x + sx), dy = x[1] - (pj.y + sy), dz = x[2] - (pj.z + sz);
       double r2 = dx * dx + dy * dy + dz * dz;
       if (side && r2 == 0.0) singular = 1;
-      double v = pj.w / sqrt(r2);
+      double v;
+      if constexpr (sizeof(R) == 4)
+        v = pj.w * (double)rsqrtf((float)r2);  // FP32 inverse distance of an FP64 difference
+      else
+        v = pj.w / sqrt(r2);
       if (side) dnew += v; else dold += v;
     }
   }
@@ -194,7 +201,11 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
         int s = lane + j * GS;
         lv[j] = s < C ? src[s] : 0.0;
       }
-      group_harmonics<GS, PM, 0, false>(lane, tb, sm.rec, x[0], x[1], x[2], 1.0, buf);
+      if (pt < 2)  // the periodic lattice term stays in FP64
+        group_harmonics<GS, PM, 0, false>(lane, tb, sm.rec, x[0], x[1], x[2], 1.0, buf);
+      else
+        group_harmonics<GS, PM, 0, false, R>(lane, tb, sm.template rec_of<R>(), (R)x[0], (R)x[1], (R)x[2],
+                                             R(1), buf);
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       double acc = 0.0;
@@ -355,8 +366,8 @@ __device__ __forceinline__ uint64_t coarse_mask(const Move &mv, int l, const int
 }
 
 // add one contribution (candidate bit) of a coarse cell to a group buffer
-template <int GS, int PM>
-__device__ __forceinline__ void coarse_contrib(const Tabs &tb, const double *rec, const Move &mv, int l,
+template <int GS, int PM, typename R>
+__device__ __forceinline__ void coarse_contrib(const Tabs &tb, const R *rec, const Move &mv, int l,
                                                const int s[3], int cand, double a, int lane, double *buf) {
   const int n = 1 << (l - 1);
   const double h = a / n;
@@ -365,10 +376,10 @@ __device__ __forceinline__ void coarse_contrib(const Tabs &tb, const double *rec
   const double *x = side ? mv.rn : mv.r;
   double v[3];
   for (int k = 0; k < 3; ++k) v[k] = (x[k] - ((s[k] + n * w[k]) + 0.5) * h) / h;
-  group_harmonics<GS, PM, 2, true>(lane, tb, rec, v[0], v[1], v[2], side ? mv.q : -mv.q, buf);
+  group_harmonics<GS, PM, 2, true, R>(lane, tb, rec, (R)v[0], (R)v[1], (R)v[2], (R)(side ? mv.q : -mv.q), buf);
 }
 
-template <int GS, int PM, int NT>
+template <int GS, int PM, typename R, int NT>
 __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS, NT> &sm) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
@@ -429,7 +440,7 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
       const double *x = side ? mv.rn : mv.r;
       double v[3];
       for (int k = 0; k < 3; ++k) v[k] = (x[k] - ((s[k] + n * w[k]) + 0.5) * h) / h;
-      group_harmonics<GS, PM, 2, true>(lane, tb, sm.rec, v[0], v[1], v[2], side ? q : -q,
+      group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)v[0], (R)v[1], (R)v[2], (R)(side ? q : -q),
                                        acc + (size_t)g * Cs);
     }
     __syncthreads();
@@ -457,10 +468,12 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
       int k = lane + j * GS;
       old[j] = k < C ? it.dst[k] : 0.0;
     }
-    group_harmonics<GS, PM, 2, false>(lane, tb, sm.rec, it.v0[0], it.v0[1], it.v0[2], it.q0, buf);
+    group_harmonics<GS, PM, 2, false, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
+                                         (R)it.q0, buf);
     if (it.two) {
       __builtin_amdgcn_wave_barrier();
-      group_harmonics<GS, PM, 2, true>(lane, tb, sm.rec, it.v1[0], it.v1[1], it.v1[2], it.q1, buf);
+      group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)it.v1[0], (R)it.v1[1],
+                                          (R)it.v1[2], (R)it.q1, buf);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -478,7 +491,7 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
 // split over NG/8 groups (partial sums added in a fixed order); level 3: 64
 // stored cells over the groups; levels >= 4: the items of both interaction
 // lists over the groups.
-template <int GS, int PM, int NT>
+template <int GS, int PM, typename R, int NT>
 __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
@@ -500,7 +513,7 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
     while (m) {
       int cand = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      if (idx++ % SPLIT2 == part) coarse_contrib<GS, PM>(tb, sm.rec, mv, 2, s3, cand, a, lane, buf);
+      if (idx++ % SPLIT2 == part) coarse_contrib<GS, PM, R>(tb, sm.template rec_of<R>(), mv, 2, s3, cand, a, lane, buf);
     }
   }
   __syncthreads();
@@ -529,7 +542,7 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
       while (m) {
         int cand = __ffsll((unsigned long long)m) - 1;
         m &= m - 1;
-        coarse_contrib<GS, PM>(tb, sm.rec, mv, 3, s3, cand, a, lane, buf);
+        coarse_contrib<GS, PM, R>(tb, sm.template rec_of<R>(), mv, 3, s3, cand, a, lane, buf);
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -552,10 +565,12 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
       int k = lane + j * GS;
       old[j] = k < C ? it.dst[k] : 0.0;
     }
-    group_harmonics<GS, PM, 2, false>(lane, tb, sm.rec, it.v0[0], it.v0[1], it.v0[2], it.q0, buf);
+    group_harmonics<GS, PM, 2, false, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
+                                         (R)it.q0, buf);
     if (it.two) {
       __builtin_amdgcn_wave_barrier();
-      group_harmonics<GS, PM, 2, true>(lane, tb, sm.rec, it.v1[0], it.v1[1], it.v1[2], it.q1, buf);
+      group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)it.v1[0], (R)it.v1[1],
+                                          (R)it.v1[2], (R)it.q1, buf);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");

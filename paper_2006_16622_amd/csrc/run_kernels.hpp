@@ -84,7 +84,7 @@ __device__ __forceinline__ void move_from_draw(const RunParams &rp, const Chain 
   }
 }
 
-template <int GS, int PM>
+template <int GS, int PM, typename R>
 __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
   constexpr int NT = WG_BATCH;
   constexpr int NG = NT / GS;
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
     locate_move_par(ch, mv);
     __syncthreads();
     const double u = s_u;
-    ProposeOut po = propose_wg<GS, PM>(ch, tb, mv, sm, [&](int lane) {
+    ProposeOut po = propose_wg<GS, PM, R>(ch, tb, mv, sm, [&](int lane) {
       if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
     });
     uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
     prev_idx = mv.idx;
     for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
     if (prev_acc) {
-      accept_all_wg<GS, PM>(ch, tb, mv, sm);
+      accept_all_wg<GS, PM, R>(ch, tb, mv, sm);
       int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, po.dE, sm);
       if (t == 0) {
         nacc += 1;
@@ -209,7 +209,7 @@ __device__ __forceinline__ bool spin_all_equal(unsigned *flags, int G, unsigned 
 
 constexpr uint64_t SPIN_LIMIT = 100000000ull * 20;  // 20 s of the 100 MHz clock
 
-template <int GS, int PM>
+template <int GS, int PM, typename R>
 __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb, RunParams rp) {
   constexpr int NT = WG_SINGLE;
   constexpr int NG = NT / GS;
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       locate_move_par(ch, mv);
       __syncthreads();
       const double u = s_u;
-      ProposeOut po = propose_wg<GS, PM>(ch, tb, mv, sm, [&](int lane) {
+      ProposeOut po = propose_wg<GS, PM, R>(ch, tb, mv, sm, [&](int lane) {
         if (lane == 0 && step + 1 < rp.steps) draw_into(rp, 0, step + 1, ch, D, nd);
       });
       uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
             st_release(seq, myseq);
           }
         } else {
-          accept_all_wg<GS, PM>(ch, tb, mv, sm);
+          accept_all_wg<GS, PM, R>(ch, tb, mv, sm);
         }
         int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, po.dE, sm);
         if (t == 0) {
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     locate_move_par(ch, mv);
     __syncthreads();
     for (int b = w - 1; b < nblk; b += G - 1) {
-      accept_block<GS, PM>(ch, tb, mv, b, sm);
+      accept_block<GS, PM, R>(ch, tb, mv, b, sm);
       __syncthreads();
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -396,7 +396,7 @@ __device__ __forceinline__ void move_direct(const Chain &ch, int64_t idx, double
   __syncthreads();
 }
 
-template <int GS, int PM>
+template <int GS, int PM, typename R>
 __global__ void __launch_bounds__(WG_SINGLE) k_propose_one(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                     double z) {
   constexpr int NT = WG_SINGLE;
@@ -405,14 +405,14 @@ __global__ void __launch_bounds__(WG_SINGLE) k_propose_one(Chain ch, Tabs tb, in
   Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
   move_direct(ch, idx, x, y, z, mv);
-  ProposeOut po = propose_wg<GS, PM>(ch, tb, mv, sm, [](int) {});
+  ProposeOut po = propose_wg<GS, PM, R>(ch, tb, mv, sm, [](int) {});
   if (threadIdx.x == 0) {
     ch.scratch[0] = po.dE;
     ch.scratch[1] = po.singular;
   }
 }
 
-template <int GS, int PM>
+template <int GS, int PM, typename R>
 __global__ void __launch_bounds__(WG_SINGLE) k_accept_blocks(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                       double z) {
   constexpr int NT = WG_SINGLE;
@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_accept_blocks(Chain ch, Tabs tb, 
   Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, false);
   move_direct(ch, idx, x, y, z, mv);
-  accept_block<GS, PM>(ch, tb, mv, blockIdx.x, sm);
+  accept_block<GS, PM, R>(ch, tb, mv, blockIdx.x, sm);
 }
 
 template <int GS, int PM>

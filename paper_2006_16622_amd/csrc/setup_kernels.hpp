@@ -159,6 +159,9 @@ __global__ void k_m2m(const Chain *chains, Tabs tb, int l) {
 // coefficients of its tile. The four wavefronts each own 6 x 2 (TO = 192)
 // or 3 x 2 (TO = 96) 16 x 16 accumulator blocks; inputs are staged through
 // LDS in chunks of 16, double-buffered, the multipoles gathered per target.
+// In FP32 the matrix cores accumulate one offset's product (at most Cs
+// terms per output) and each offset's partial sum is added into an FP64
+// accumulator, so the rounding of the 189-offset sum is FP64's.
 template <typename T>
 struct Mfma;
 template <>
@@ -263,10 +266,19 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
     for (int e = 0; e < 4; ++e) Bs[buf][brow + e][bt] = rb[e];
   };
   typename MF::acc_t acc[RB][2];
+  constexpr bool split = sizeof(T) == 4;
+  double accd[split ? RB : 1][2][4];
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (typename MF::acc_t){0, 0, 0, 0};
+  if constexpr (split)
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) accd[i][j][v] = 0.0;
   fetch(0);
   stash(0);
   __syncthreads();
@@ -282,6 +294,18 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
         const T a = As[buf][kr][ro + 16 * i + (lane & 15)];
         acc[i][0] = MF::mma(a, b0, acc[i][0]);
         acc[i][1] = MF::mma(a, b1, acc[i][1]);
+      }
+    }
+    if constexpr (split) {
+      if ((it + 1) % nq == 0) {  // the last chunk of an offset: fold into FP64
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) accd[i][j][v] += (double)acc[i][j][v];
+            acc[i][j] = (typename MF::acc_t){0, 0, 0, 0};
+          }
       }
     }
     if (it + 1 < total) stash(buf ^ 1);
@@ -301,7 +325,12 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = j0 + ro + 16 * i + MF::row(lane, v);
-        if (r < Cs) dst[r] = (double)acc[i][j][v];
+        double val;
+        if constexpr (split)
+          val = accd[i][j][v];
+        else
+          val = acc[i][j][v];
+        if (r < Cs) dst[r] = val;
       }
   }
 }
