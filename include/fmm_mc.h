@@ -115,7 +115,9 @@ typedef struct {
   const double *chain_max_step; /* host array of n_chains half-widths, or NULL */
   int64_t t0;       /* first step index of the Philox counter */
   int32_t mode;     /* 0 = automatic, 1 = one workgroup per chain, 2 = whole GPU per chain */
-  int32_t reserved;
+  int32_t resetup_every; /* > 0: after this many accepted moves a chain's expansions are rebuilt
+                          * from its positions in FP64 (fmm_mc_resetup) before it continues;
+                          * 0 = never. Bounds the drift of the accumulated updates. */
   /* optional traces (device pointers, NULL = off), indexed [chain * steps + t] */
   int64_t *trace_idx;
   double *trace_newpos; /* 3 per step */

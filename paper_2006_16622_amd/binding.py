@@ -28,7 +28,7 @@ class FmmMcError(RuntimeError):
 class RunOpts(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("max_step", ctypes.c_double),
                 ("chain_max_step", ctypes.POINTER(ctypes.c_double)), ("t0", ctypes.c_int64),
-                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("resetup_every", ctypes.c_int32),
                 ("trace_idx", ctypes.c_void_p), ("trace_newpos", ctypes.c_void_p),
                 ("trace_dE", ctypes.c_void_p), ("trace_acc", ctypes.c_void_p)]
 
@@ -238,7 +238,7 @@ def setup_batch(systems, p: int, flags: int = 0, device: str = "cuda:0", stream=
 
 
 def run_chains(chains, steps: int, seed: int, beta: float, max_step, t0: int = 0, mode: int = 0,
-               traces: bool = False):
+               traces: bool = False, resetup_every: int = 0):
     """fmm_mc_run over a list of Chain objects (same device and stream).
     With traces, device buffers (torch) are allocated and returned as numpy."""
     import torch
@@ -252,6 +252,7 @@ def run_chains(chains, steps: int, seed: int, beta: float, max_step, t0: int = 0
     opts.chain_max_step = _d(ms)
     opts.t0 = int(t0)
     opts.mode = int(mode)
+    opts.resetup_every = int(resetup_every)
     tr = None
     if traces:
         dev = chains[0].device

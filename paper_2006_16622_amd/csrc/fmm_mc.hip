@@ -639,6 +639,7 @@ int fmm_mc_resetup(fmm_mc_t h) {
     S.st = h->cap_stream;
     S.restage = true;
     S.energy_mode = 1;
+    S.fp32_m2l = false;  // the re-setup is FP64 in every mode
     HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_setup(S);
     hipGraph_t g = nullptr;
@@ -709,11 +710,14 @@ int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *
   return status ? status : FMM_MC_OK;
 }
 
-// shared driver of fmm_mc_run and fmm_mc_replay
+// shared driver of fmm_mc_run and fmm_mc_replay. With resetup_every > 0 a
+// chain stops after that many accepts, is re-set up (its captured setup
+// graph, FP64) and continues where it stopped, until every chain has done
+// `steps` steps; the chains still running are relaunched together.
 static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t seed, int64_t t0, double beta,
-                      const double *steps_h, int mode, const int64_t *l_idx, const double *l_pos,
-                      const double *l_u, int64_t *tr_idx, double *tr_pos, double *tr_dE, uint8_t *tr_acc,
-                      int32_t *tr_leaf, fmm_mc_stats *stats) {
+                      const double *steps_h, int mode, int64_t resetup_every, const int64_t *l_idx,
+                      const double *l_pos, const double *l_u, int64_t *tr_idx, double *tr_pos, double *tr_dE,
+                      uint8_t *tr_acc, int32_t *tr_leaf, fmm_mc_stats *stats) {
   fmm_mc_t h0 = chains[0];
   for (int c = 0; c < n_chains; ++c) {
     if (!chains[c] || !chains[c]->ready) return FMM_MC_ESTATE;
@@ -725,27 +729,49 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   hipStream_t st = h0->stream;
   const Tabs &tb = h0->tables->tabs;
   const int GS = h0->GS;
-  // device scratch for per-chain parameters: the first chain's workspace
-  // stats area holds max_step (n_chains <= 4096 supported through a
-  // temporary allocation otherwise)
+  const bool single = (n_chains == 1 && mode != 1);
+  const int NT = single ? WG_SINGLE : WG_BATCH;
+  const size_t shm = smem_bytes(GS, tb, NT);
+  // launch arguments in stream-ordered device memory, freed at the end
   double *d_step = nullptr, *d_stats = nullptr;
   Chain *d_chains = nullptr;
+  int64_t *d_first = nullptr;
+  int *d_id = nullptr;
   int64_t *d_lidx = nullptr;
   double *d_lpos = nullptr, *d_lu = nullptr;
-  HIPCHK(hipMallocAsync((void **)&d_step, sizeof(double) * n_chains, st));
-  HIPCHK(hipMallocAsync((void **)&d_stats, sizeof(double) * 8 * n_chains, st));
-  HIPCHK(hipMallocAsync((void **)&d_chains, sizeof(Chain) * n_chains, st));
-  std::vector<Chain> hc(n_chains);
-  for (int c = 0; c < n_chains; ++c) hc[c] = chains[c]->ch;
-  HIPCHK(hipMemcpyAsync(d_step, steps_h, sizeof(double) * n_chains, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_chains, hc.data(), sizeof(Chain) * n_chains, hipMemcpyHostToDevice, st));
+  auto release = [&]() {
+    (void)hipFreeAsync(d_step, st);
+    (void)hipFreeAsync(d_stats, st);
+    (void)hipFreeAsync(d_chains, st);
+    (void)hipFreeAsync(d_first, st);
+    (void)hipFreeAsync(d_id, st);
+    if (d_lidx) {
+      (void)hipFreeAsync(d_lidx, st);
+      (void)hipFreeAsync(d_lpos, st);
+      (void)hipFreeAsync(d_lu, st);
+    }
+    (void)hipStreamSynchronize(st);
+  };
+#define RUNCHK(x)                   \
+  do {                              \
+    if ((x) != hipSuccess) {        \
+      release();                    \
+      return FMM_MC_EDEVICE;        \
+    }                               \
+  } while (0)
+  RUNCHK(hipMallocAsync((void **)&d_step, sizeof(double) * n_chains, st));
+  RUNCHK(hipMallocAsync((void **)&d_stats, sizeof(double) * 8 * n_chains, st));
+  RUNCHK(hipMallocAsync((void **)&d_chains, sizeof(Chain) * n_chains, st));
+  RUNCHK(hipMallocAsync((void **)&d_first, sizeof(int64_t) * n_chains, st));
+  RUNCHK(hipMallocAsync((void **)&d_id, sizeof(int) * n_chains, st));
+  RUNCHK(hipMemcpyAsync(d_step, steps_h, sizeof(double) * n_chains, hipMemcpyHostToDevice, st));
   if (l_idx) {
-    HIPCHK(hipMallocAsync((void **)&d_lidx, sizeof(int64_t) * steps, st));
-    HIPCHK(hipMallocAsync((void **)&d_lpos, sizeof(double) * 3 * steps, st));
-    HIPCHK(hipMallocAsync((void **)&d_lu, sizeof(double) * steps, st));
-    HIPCHK(hipMemcpyAsync(d_lidx, l_idx, sizeof(int64_t) * steps, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_lpos, l_pos, sizeof(double) * 3 * steps, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_lu, l_u, sizeof(double) * steps, hipMemcpyHostToDevice, st));
+    RUNCHK(hipMallocAsync((void **)&d_lidx, sizeof(int64_t) * steps, st));
+    RUNCHK(hipMallocAsync((void **)&d_lpos, sizeof(double) * 3 * steps, st));
+    RUNCHK(hipMallocAsync((void **)&d_lu, sizeof(double) * steps, st));
+    RUNCHK(hipMemcpyAsync(d_lidx, l_idx, sizeof(int64_t) * steps, hipMemcpyHostToDevice, st));
+    RUNCHK(hipMemcpyAsync(d_lpos, l_pos, sizeof(double) * 3 * steps, hipMemcpyHostToDevice, st));
+    RUNCHK(hipMemcpyAsync(d_lu, l_u, sizeof(double) * steps, hipMemcpyHostToDevice, st));
   }
   RunParams rp{};
   rp.steps = steps;
@@ -753,6 +779,9 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   rp.seed = seed;
   rp.beta = beta;
   rp.max_step = d_step;
+  rp.first = d_first;
+  rp.chain_id = d_id;
+  rp.acc_limit = resetup_every > 0 ? resetup_every : 0;
   rp.list_idx = d_lidx;
   rp.list_pos = d_lpos;
   rp.list_u = d_lu;
@@ -762,72 +791,110 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   rp.tr_acc = tr_acc;
   rp.tr_leaf = tr_leaf;
   rp.stats = d_stats;
-  bool single = (n_chains == 1 && mode != 1);
-  const int NT = single ? WG_SINGLE : WG_BATCH;
-  const size_t shm = smem_bytes(GS, tb, NT);
-  if (single) hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 512);
-  HIPCHK(hipEventRecord(h0->ev0, st));
+  int G = 1;
   if (single) {
     const int NG = NT / GS;
-    int G = accept_blocks(h0->ch.L, NG) + 1;  // workgroup 0 proposes, the others update
+    G = accept_blocks(h0->ch.L, NG) + 1;  // workgroup 0 proposes, the others update
     int ncu = 0, per = 0;
-    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
+    RUNCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
     hipError_t oe = hipSuccess;
     with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
       oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &per, k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>, NT, shm);
     });
-    HIPCHK(oe);
+    RUNCHK(oe);
     int cap = std::max(1, ncu * std::max(per, 1));
     G = std::max(1, std::min(G, std::min(cap, ncu)));
-    Chain chv = h0->ch;
-    void *args[] = {&chv, (void *)&tb, &rp};
-    hipError_t e = hipSuccess;
-    with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
-      e = hipLaunchCooperativeKernel(
-          (const void *)k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>,
-          dim3(G), dim3(NT), args, shm, st);
-    });
-    if (e != hipSuccess) return FMM_MC_EDEVICE;
-  } else {
-    with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value,
-                                                       typename decltype(rt)::type>),
-                         dim3(n_chains), dim3(NT), shm, st, d_chains, tb, rp);
-    });
   }
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipEventRecord(h0->ev1, st));
-  std::vector<double> hs(8 * n_chains);
-  HIPCHK(hipMemcpyAsync(hs.data(), d_stats, sizeof(double) * 8 * n_chains, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipFreeAsync(d_step, st));
-  HIPCHK(hipFreeAsync(d_stats, st));
-  HIPCHK(hipFreeAsync(d_chains, st));
-  if (l_idx) {
-    HIPCHK(hipFreeAsync(d_lidx, st));
-    HIPCHK(hipFreeAsync(d_lpos, st));
-    HIPCHK(hipFreeAsync(d_lu, st));
-  }
-  HIPCHK(hipStreamSynchronize(st));
-  float ms = 0;
-  HIPCHK(hipEventElapsedTime(&ms, h0->ev0, h0->ev1));
-  h0->last_ms[0] = ms;
+  std::vector<int64_t> done(n_chains, 0);
+  std::vector<double> acc(8 * n_chains, 0.0);  // accumulated stats per chain
+  std::vector<int> ids;
+  std::vector<int64_t> firsts;
+  std::vector<Chain> hc;
+  std::vector<double> hs;
+  double kernel_ms = 0.0;
   int rc = FMM_MC_OK;
-  for (int c = 0; c < n_chains; ++c) {
-    double U[2];
-    HIPCHK(hipMemcpy(U, chains[c]->ch.U, sizeof(U), hipMemcpyDeviceToHost));
-    if (stats) {
-      stats[c].proposed = (int64_t)hs[8 * c];
-      stats[c].accepted = (int64_t)hs[8 * c + 1];
-      stats[c].singular = (int64_t)hs[8 * c + 2];
-      stats[c].dE_sum = hs[8 * c + 3];
-      stats[c].energy = U[0];
-      stats[c].status = (int32_t)hs[8 * c + 4];
-      stats[c].t_propose_us = hs[8 * c + 5];
-      stats[c].t_accept_us = hs[8 * c + 6];
-      stats[c].t_wait_us = hs[8 * c + 7];
+  while (rc == FMM_MC_OK) {
+    ids.clear();
+    firsts.clear();
+    hc.clear();
+    for (int c = 0; c < n_chains; ++c)
+      if (done[c] < steps) {
+        ids.push_back(c);
+        firsts.push_back(done[c]);
+        hc.push_back(chains[c]->ch);
+      }
+    const int na = (int)ids.size();
+    if (na == 0) break;
+    RUNCHK(hipMemcpyAsync(d_chains, hc.data(), sizeof(Chain) * na, hipMemcpyHostToDevice, st));
+    RUNCHK(hipMemcpyAsync(d_first, firsts.data(), sizeof(int64_t) * na, hipMemcpyHostToDevice, st));
+    RUNCHK(hipMemcpyAsync(d_id, ids.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
+    if (single) hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 512);
+    RUNCHK(hipEventRecord(h0->ev0, st));
+    if (single) {
+      Chain chv = h0->ch;
+      void *args[] = {&chv, (void *)&tb, &rp};
+      hipError_t e = hipSuccess;
+      with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
+        e = hipLaunchCooperativeKernel(
+            (const void *)k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>,
+            dim3(G), dim3(NT), args, shm, st);
+      });
+      RUNCHK(e);
+    } else {
+      with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value,
+                                                         typename decltype(rt)::type>),
+                           dim3(na), dim3(NT), shm, st, d_chains, tb, rp);
+      });
     }
-    if ((int)hs[8 * c + 4] != 0) rc = (int)hs[8 * c + 4];
+    RUNCHK(hipGetLastError());
+    RUNCHK(hipEventRecord(h0->ev1, st));
+    hs.assign(8 * na, 0.0);
+    RUNCHK(hipMemcpyAsync(hs.data(), d_stats, sizeof(double) * 8 * na, hipMemcpyDeviceToHost, st));
+    RUNCHK(hipStreamSynchronize(st));
+    float ms = 0;
+    RUNCHK(hipEventElapsedTime(&ms, h0->ev0, h0->ev1));
+    kernel_ms += ms;
+    for (int k = 0; k < na; ++k) {
+      const int c = ids[k];
+      const double *v = &hs[8 * k];
+      for (int j = 0; j < 8; ++j)
+        if (j != 4) acc[8 * c + j] += v[j];
+      done[c] += (int64_t)v[0];
+      if ((int)v[4] != 0) {
+        acc[8 * c + 4] = v[4];
+        rc = (int)v[4];
+      }
+    }
+    if (rc != FMM_MC_OK) break;
+    // chains that stopped at the accept limit with steps left: re-setup
+    for (int k = 0; k < na && rc == FMM_MC_OK; ++k) {
+      const int c = ids[k];
+      if (done[c] < steps) {
+        int r = fmm_mc_resetup(chains[c]);
+        if (r) rc = r;
+      }
+    }
+  }
+#undef RUNCHK
+  release();
+  h0->last_ms[0] = kernel_ms;
+  for (int c = 0; c < n_chains; ++c) {
+    double U[2] = {0, 0};
+    if (hipMemcpy(U, chains[c]->ch.U, sizeof(U), hipMemcpyDeviceToHost) != hipSuccess) return FMM_MC_EDEVICE;
+    if (stats) {
+      const double *v = &acc[8 * c];
+      stats[c].proposed = (int64_t)v[0];
+      stats[c].accepted = (int64_t)v[1];
+      stats[c].singular = (int64_t)v[2];
+      stats[c].dE_sum = v[3];
+      stats[c].energy = U[0];
+      stats[c].status = (int32_t)v[4];
+      stats[c].t_propose_us = v[5];
+      stats[c].t_accept_us = v[6];
+      stats[c].t_wait_us = v[7];
+    }
   }
   return rc;
 }
@@ -842,8 +909,10 @@ int fmm_mc_run(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t seed, con
     if (!(st[c] >= 0.0) || !std::isfinite(st[c])) return FMM_MC_EINVAL;
   }
   if (steps == 0) return FMM_MC_OK;
-  return run_chains(chains, n_chains, steps, seed, opts->t0, opts->beta, st.data(), opts->mode, nullptr, nullptr,
-                    nullptr, opts->trace_idx, opts->trace_newpos, opts->trace_dE, opts->trace_acc, nullptr, stats);
+  if (opts->resetup_every < 0) return FMM_MC_EINVAL;
+  return run_chains(chains, n_chains, steps, seed, opts->t0, opts->beta, st.data(), opts->mode, opts->resetup_every,
+                    nullptr, nullptr, nullptr, opts->trace_idx, opts->trace_newpos, opts->trace_dE, opts->trace_acc,
+                    nullptr, stats);
 }
 
 int fmm_mc_replay(fmm_mc_t h, int64_t m, const int64_t *idx, const double *new_pos, const double *u, double beta,
@@ -863,7 +932,7 @@ int fmm_mc_replay(fmm_mc_t h, int64_t m, const int64_t *idx, const double *new_p
   HIPCHK(hipMallocAsync((void **)&d_leaf, sizeof(int32_t) * m, h->stream));
   double zero = 0.0;
   fmm_mc_t hs[1] = {h};
-  int rc = run_chains(hs, 1, m, 0, 0, beta, &zero, 0, idx, new_pos, u, nullptr, nullptr, d_dE, d_acc, d_leaf,
+  int rc = run_chains(hs, 1, m, 0, 0, beta, &zero, 0, 0, idx, new_pos, u, nullptr, nullptr, d_dE, d_acc, d_leaf,
                       nullptr);
   if (rc == FMM_MC_OK) {
     if (dE) HIPCHK(hipMemcpyAsync(dE, d_dE, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));

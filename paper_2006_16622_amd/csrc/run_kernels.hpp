@@ -24,11 +24,19 @@
 
 namespace fmmdev {
 
+// A run is `steps` MH steps per chain; a launch may cover part of it: slot
+// k of the launch (blockIdx.x, or the single chain) is chain chain_id[k] of
+// the run and resumes at step first[k]. A chain stops early once it has
+// accepted acc_limit moves in this launch (the caller then re-sets it up
+// and launches the rest).
 struct RunParams {
   int64_t steps, t0;
   uint64_t seed;
   double beta;
-  const double *max_step;  // per chain
+  const double *max_step;  // per chain of the run
+  const int64_t *first;    // per slot, null: 0
+  const int *chain_id;     // per slot, null: the slot
+  int64_t acc_limit;       // 0: none
   // fixed-list source (replay) when list_idx != nullptr
   const int64_t *list_idx;
   const double *list_pos;
@@ -94,8 +102,10 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
   __shared__ int s_acc;
   __shared__ double s_u;
   __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
-  const int c = blockIdx.x, t = threadIdx.x;
-  if (t == 0) chl = chains[c];
+  const int slot = blockIdx.x, t = threadIdx.x;
+  const int c = rp.chain_id ? rp.chain_id[slot] : slot;
+  const int64_t s0 = rp.first ? rp.first[slot] : 0;
+  if (t == 0) chl = chains[slot];
   __syncthreads();
   const Chain &ch = chl;
   Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
@@ -107,9 +117,10 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
   bool prev_acc = false;
   int prev_idx = -1;
   double prev_rn[3] = {0, 0, 0};
-  if (t == 0 && rp.steps > 0) draw_into(rp, c, 0, ch, D, nd);
+  int64_t acc_launch = 0;
+  if (t == 0 && s0 < rp.steps) draw_into(rp, c, s0, ch, D, nd);
   __syncthreads();
-  for (int64_t step = 0; step < rp.steps; ++step) {
+  for (int64_t step = s0; step < rp.steps; ++step) {
     uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
     if (t == 0) {
       move_from_draw(rp, ch, nd, prev_acc, prev_idx, prev_rn, mv);
@@ -156,12 +167,13 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
         status = -7;
         break;
       }
+      if (rp.acc_limit && ++acc_launch >= rp.acc_limit) break;
     }
   }
   __syncthreads();
   writeback_lds(ch, tb, sm);
   if (t == 0) {
-    double *st = rp.stats + 8 * c;
+    double *st = rp.stats + 8 * slot;
     st[0] = nprop;
     st[1] = nacc;
     st[2] = nsing;
@@ -230,7 +242,8 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   stage_lds(ch, tb, sm, w == 0);
   __syncthreads();
   if (w == 0) {
-    const double D = rp.max_step[0];
+    const int c = rp.chain_id ? rp.chain_id[0] : 0;
+    const double D = rp.max_step[c];
     double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
     int status = 0;
     unsigned myseq = 0;
@@ -238,9 +251,11 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     bool prev_acc = false;
     int prev_idx = -1;
     double prev_rn[3] = {0, 0, 0};
-    if (t == 0 && rp.steps > 0) draw_into(rp, 0, 0, ch, D, nd);
+    const int64_t s0 = rp.first ? rp.first[0] : 0;
+    int64_t acc_launch = 0;
+    if (t == 0 && s0 < rp.steps) draw_into(rp, c, s0, ch, D, nd);
     __syncthreads();
-    for (int64_t step = 0; step < rp.steps; ++step) {
+    for (int64_t step = s0; step < rp.steps; ++step) {
       uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
       if (t == 0) {
         move_from_draw(rp, ch, nd, prev_acc, prev_idx, prev_rn, mv);
@@ -251,7 +266,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       __syncthreads();
       const double u = s_u;
       ProposeOut po = propose_wg<GS, PM, R>(ch, tb, mv, sm, [&](int lane) {
-        if (lane == 0 && step + 1 < rp.steps) draw_into(rp, 0, step + 1, ch, D, nd);
+        if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
       });
       uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
       tick_prop += t_1 - t_0;
@@ -260,14 +275,15 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
         s_acc = acc;
         nprop += 1;
         nsing += po.singular;
-        if (rp.tr_idx) rp.tr_idx[step] = mv.idx;
+        const int64_t o = (int64_t)c * rp.steps + step;
+        if (rp.tr_idx) rp.tr_idx[o] = mv.idx;
         if (rp.tr_pos)
-          for (int k = 0; k < 3; ++k) rp.tr_pos[3 * step + k] = mv.rn[k];
-        if (rp.tr_dE) rp.tr_dE[step] = po.dE;
-        if (rp.tr_acc) rp.tr_acc[step] = (uint8_t)acc;
+          for (int k = 0; k < 3; ++k) rp.tr_pos[3 * o + k] = mv.rn[k];
+        if (rp.tr_dE) rp.tr_dE[o] = po.dE;
+        if (rp.tr_acc) rp.tr_acc[o] = (uint8_t)acc;
         if (rp.tr_leaf) {
           int n = 1 << (ch.L - 1);
-          rp.tr_leaf[step] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
+          rp.tr_leaf[o] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
         }
         if (acc && G > 1) {
           mb[0] = (double)mv.idx;
@@ -316,6 +332,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
           status = -7;
           break;
         }
+        if (rp.acc_limit && ++acc_launch >= rp.acc_limit) break;
       }
     }
     if (G > 1 && t == 0) {

@@ -85,3 +85,56 @@ def test_resetup_graph_replays_equal_eager_setup():
         r = gpu.positions()[i] + d
         assert gpu.propose(i, r) == fresh.propose(i, r)
         fresh.close()
+
+
+def _oracle_with_resetups(wl, steps, every, chain=0):
+    """the oracle's chain with a fresh setup from its positions after every
+    `every` accepted moves (the re-setup the run loop performs)"""
+    orc = O.Multilevel(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+    out = {k: [] for k in ("idx", "newpos", "dE", "u", "acc")}
+    since = 0
+    for t in range(steps):
+        tr = orc.run(wl.seed, chain, t, 1, wl.beta, wl.max_step)
+        for k in out:
+            out[k].append(tr[k][0])
+        if tr["acc"][0]:
+            since += 1
+            if since == every and t + 1 < steps:
+                orc = O.Multilevel(orc.positions(), wl.q, wl.box, wl.depth, wl.p)
+                since = 0
+    return {k: np.array(v) for k, v in out.items()}, orc
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_run_with_periodic_resetup_matches_oracle(mode):
+    from paper_2006_16622_amd import Chain, run_chains
+    wl = W.uniform(600, 2, 6, 0.05, seed=45, key=14)
+    steps, every = 240, 20
+    ref, orc = _oracle_with_resetups(wl, steps, every)
+    assert ref["acc"].sum() > 3 * every
+    gpu = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+    st, tr = run_chains([gpu], steps, wl.seed, wl.beta, wl.max_step, mode=mode, traces=True,
+                        resetup_every=every)
+    assert st[0]["status"] == 0 and st[0]["proposed"] == steps
+    assert np.array_equal(tr["idx"][0], ref["idx"])
+    assert np.array_equal(tr["newpos"][0], ref["newpos"])
+    assert np.array_equal(tr["acc"][0], ref["acc"])
+    rms = np.sqrt(np.mean(ref["dE"] ** 2))
+    assert np.abs(tr["dE"][0] - ref["dE"]).max() <= 1e-10 * rms
+    assert np.array_equal(gpu.positions(), orc.positions())
+
+
+def test_batched_run_with_periodic_resetup_matches_oracle():
+    from paper_2006_16622_amd import Chain, run_chains
+    wls = [W.uniform(500 + 100 * k, 2, 6, 0.05, seed=46, key=15 + k) for k in range(3)]
+    steps, every = 200, 15
+    chains = [Chain(w.pos, w.q, w.box, w.depth, w.p) for w in wls]
+    st, tr = run_chains(chains, steps, wls[0].seed, 1.0, [w.max_step for w in wls], mode=1, traces=True,
+                        resetup_every=every)
+    for k, w in enumerate(wls):
+        ref, _ = _oracle_with_resetups(w, steps, every, chain=k)
+        assert st[k]["status"] == 0 and st[k]["proposed"] == steps
+        assert np.array_equal(tr["acc"][k], ref["acc"])
+        assert np.array_equal(tr["newpos"][k], ref["newpos"])
+        rms = np.sqrt(np.mean(ref["dE"] ** 2))
+        assert np.abs(tr["dE"][k] - ref["dE"]).max() <= 1e-10 * rms
