@@ -6,9 +6,17 @@ the periodic unit cube, octree depth 5, degree p = 12, beta = 1, displacement
 uniform in [-0.3/46, 0.3/46)^3, one chain, FP64. A step is one whole MH step
 (proposal energy, decision, and on acceptance the O(189 p^2 L) update of the
 interaction-list expansions plus bookkeeping), all inside one persistent
-kernel. The setup (P2M, M2M, M2L, lattice) is timed separately. The batched
-form (256 independent chains of uneven size and depth in one launch) is
-measured in the same run and reported as its aggregate steps/s.
+kernel. The setup (P2M, M2M, M2L, lattice) is timed separately.
+
+Also measured in the same run and reported beside the headline value:
+* the same chain in mixed precision with an FP64 re-setup every 10^4
+  accepts;
+* the batched form: 256 independent chains of uneven size and depth, set up
+  in one pass and run in one launch, in FP64 and in mixed precision, as
+  aggregate steps/s;
+* in the cpu_baseline leg: the FP64 oracle's per-step rate, the Ewald
+  oracle's, and the dE error of both precisions against Ewald on proposals
+  from the initial rock-salt state.
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -118,6 +126,26 @@ def algorithmic_bytes(wl, pos_before, tr_idx, tr_pos, tr_acc, sample=1500):
     return prop, acc_bytes, float(np.mean(tr_acc)), mean_t
 
 
+def batched_algorithmic_bytes(wls, st, sample=40):
+    """algorithmic bytes of a batched run: per chain its proposals and its
+    accepts (mean distinct interaction-list targets per accept estimated on
+    `sample` moves of the chain's own step size from its initial state)"""
+    total = 0.0
+    ilo = il_offsets()
+    for w, s in zip(wls, st):
+        C = (w.p + 1) ** 2
+        L = w.depth + 1
+        mean_leaf = w.n / 8 ** w.depth
+        prop = 2 * w.depth * C * 8 + 2 * 27 * (mean_leaf * 36 + 4) + 2 * C * 8
+        g = np.random.default_rng(w.chain)
+        idx = g.integers(0, w.n, sample)
+        tg = [accept_targets(w.pos[i], np.mod(w.pos[i] + g.uniform(-w.max_step, w.max_step, 3), w.box),
+                             w.box, L, ilo) for i in idx]
+        acc = float(np.mean(tg)) * C * 8 * 2 + 2 * C * 8 * 3
+        total += s["proposed"] * prop + s["accepted"] * acc
+    return total
+
+
 def cpu_baseline(wl, nu, nprop=8000, nacc=1000):
     """The FP64 oracle timed on one host core: proposals and accepts of the
     same workload timed separately on a state whose expansions are not
@@ -140,38 +168,90 @@ def cpu_baseline(wl, nu, nprop=8000, nacc=1000):
         m.accept(i, wl.pos[i] + d)
     ta = (time.perf_counter() - t0) / nacc
     step = tp + nu * ta
-    return {"value": 1.0 / step, "unit": "MH steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nprop} proposals and {nacc} accepts of the rocksalt workload on one core "
-                      f"(expansions not initialised; lattice moments formed in {t_setup:.1f} s), "
-                      f"t_prop={tp*1e3:.3f} ms, t_acc={ta*1e3:.3f} ms, combined at nu={nu:.3f}"}
-
-
-def run_batched(seed=4, steps=10000, nchains=256):
-    import workloads as W
-    from paper_2006_16622_amd import Chain, run_chains
-    import torch
-    chains, wls = [], []
+    out = {"value": 1.0 / step, "unit": "MH steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{nprop} proposals and {nacc} accepts of the rocksalt workload on one core "
+                     f"(expansions not initialised; lattice moments formed in {t_setup:.1f} s), "
+                     f"t_prop={tp*1e3:.3f} ms, t_acc={ta*1e3:.3f} ms, combined at nu={nu:.3f}"}
+    m.close()
+    # the Ewald oracle (tin-foil, structure-factor updates): its per-step
+    # rate, and the dE of the GPU in both precisions against it
+    from paper_2006_16622_amd import FMM_MC_MIXED, Chain
     t0 = time.perf_counter()
-    for c in range(nchains):
-        wl = W.batched_chain(c, nchains, steps=steps)
-        wls.append(wl)
-        chains.append(Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p))
+    ew = O.Ewald(wl.pos, wl.q, wl.box)
+    t_ew_setup = time.perf_counter() - t0
+    moves = []
+    for t in range(200):
+        i, d, u = O.draw(wl.seed, 0, t, wl.n, wl.max_step)
+        moves.append((i, wl.pos[i] + d))
+    t0 = time.perf_counter()
+    ref = np.array([ew.propose(i, r) for i, r in moves])
+    tpe = (time.perf_counter() - t0) / len(moves)
+    t0 = time.perf_counter()
+    for i, r in moves[:100]:
+        ew.accept(i, r)
+    tae = (time.perf_counter() - t0) / 100
+    errs = {}
+    for name, flags in (("f64", 0), ("mixed", FMM_MC_MIXED)):
+        ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
+        de = np.array([ch.propose(i, r) for i, r in moves])
+        ch.close()
+        errs[name] = float(np.sqrt(np.mean((de - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
+    out["ewald"] = {"value": 1.0 / (tpe + nu * tae), "unit": "MH steps/s", "cores": 1, "kind": "oracle",
+                    "setup_s": t_ew_setup, "t_prop_ms": tpe * 1e3, "t_acc_ms": tae * 1e3}
+    out["dE_rel_rms_err_vs_ewald"] = errs
+    out["dE_err_sample"] = "200 proposals of the Philox stream from the initial rock-salt state, p = 12"
+    return out
+
+
+def run_batched(seed=4, steps=10000, nchains=256, flags=0, resetup_every=0):
+    import workloads as W
+    from paper_2006_16622_amd import run_chains, setup_batch
+    import torch
+    wls = [W.batched_chain(c, nchains, steps=steps) for c in range(nchains)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chains = setup_batch([(w.pos, w.q, w.box, w.depth) for w in wls], wls[0].p, flags=flags)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    m2l_ms = chains[0].last_timing()[1]
     # warmup a few steps (kernel load), then the timed launch
     run_chains(chains, 20, seed, 1.0, [w.max_step for w in wls], t0=0, mode=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = run_chains(chains, steps, seed, 1.0, [w.max_step for w in wls], t0=20, mode=1)
+    st = run_chains(chains, steps, seed, 1.0, [w.max_step for w in wls], t0=20, mode=1,
+                    resetup_every=resetup_every)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kern = chains[0].last_timing()[0] * 1e-3
     acc = sum(s["accepted"] for s in st)
+    abytes = batched_algorithmic_bytes(wls, st)
+    for c in chains:
+        c.close()
     return {"value": nchains * steps / dt, "unit": "MH steps/s", "chains": nchains, "steps_per_chain": steps,
+            "precision": "mixed" if flags else "f64", "resetup_every": resetup_every,
             "kernel_s": kern, "wall_s": dt, "nu": acc / (nchains * steps), "setup_s": t_setup,
+            "setup_m2l_ms": m2l_ms,
+            "roofline": {"bound": "hbm", "achieved": abytes / kern / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": abytes / kern / 1e9 / HBM_PEAK_GBS, "kernel": "k_run_batched",
+                         "algorithmic_bytes": abytes},
             "n_range": [min(w.n for w in wls), max(w.n for w in wls)],
             "depths": {str(d): sum(1 for w in wls if w.depth == d) for d in sorted({w.depth for w in wls})},
             "status": [s["status"] for s in st if s["status"] != 0][:4]}
+
+
+def run_single_mixed(wl, steps, warmup, resetup_every=10000):
+    from paper_2006_16622_amd import FMM_MC_MIXED, Chain, run_chains
+    import torch
+    ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=FMM_MC_MIXED)
+    run_chains([ch], warmup, wl.seed, wl.beta, wl.max_step, t0=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = run_chains([ch], steps, wl.seed, wl.beta, wl.max_step, t0=warmup, resetup_every=resetup_every)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ch.close()
+    return {"value": steps / dt, "unit": "MH steps/s", "precision": "mixed", "resetup_every": resetup_every,
+            "accepted": st[0]["accepted"], "status": st[0]["status"]}
 
 
 def main():
@@ -255,10 +335,16 @@ def main():
                      "bytes_per_proposal": prop_b, "bytes_per_accept": acc_b,
                      "targets_per_accept": mean_t},
     }
+    log("[bench] single chain, mixed precision")
+    out["single_mixed"] = run_single_mixed(wl, args.steps, args.warmup)
+    log(f"[bench] single chain mixed {out['single_mixed']['value']:.1f} steps/s")
     if not args.no_batched:
-        log("[bench] batched 256 chains")
+        log("[bench] batched 256 chains, FP64")
         out["batched"] = run_batched(steps=args.batched_steps)
         log(f"[bench] batched {out['batched']['value']:.1f} steps/s")
+        log("[bench] batched 256 chains, mixed precision")
+        out["batched_mixed"] = run_batched(steps=args.batched_steps, flags=1, resetup_every=10000)
+        log(f"[bench] batched mixed {out['batched_mixed']['value']:.1f} steps/s")
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, out["config"]["acceptance"])
