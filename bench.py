@@ -295,7 +295,9 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     m2l_ms = ch.last_timing()[1]
-    log(f"[bench] setup {t_setup*1e3:.1f} ms (M2L {m2l_ms:.2f} ms); warmup {args.warmup}")
+    log(f"[bench] setup {t_setup*1e3:.1f} ms (M2L {m2l_ms:.2f} ms); autotune")
+    tune = ch.autotune(steps=2000, beta=wl.beta, max_step=wl.max_step)
+    log(f"[bench] autotune: M2L rows {tune['m2l_rows']}, helpers {tune['helpers']}; warmup {args.warmup}")
     run_chains([ch], args.warmup, wl.seed, wl.beta, wl.max_step, t0=0, mode=args.mode)
     torch.cuda.synchronize()
     pos_before = ch.positions()
@@ -327,6 +329,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "n": wl.n, "depth": wl.depth, "p": wl.p, "beta": wl.beta,
                    "max_step": wl.max_step, "chains": 1, "setup_ms": t_setup * 1e3, "setup_m2l_ms": m2l_ms,
+                   "autotune": tune,
                    "acceptance": s0["accepted"] / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.steps, args.warmup),

@@ -180,6 +180,32 @@ int fmm_mc_dump_locals(fmm_mc_t h, int level, double *out);
  * FMM_MC_EOVERFLOW. */
 int fmm_mc_resetup(fmm_mc_t h);
 
+/* Result of fmm_mc_autotune. */
+typedef struct {
+  int32_t m2l_rows;              /* chosen M2L output rows per workgroup: 96 or 192 */
+  int32_t helpers;               /* chosen helper workgroups of the whole-GPU run */
+  int32_t n_helper_candidates;
+  int32_t pad;
+  double m2l_ms[2];              /* M2L time (ms) with 96 and with 192 rows per workgroup */
+  int32_t helper_candidates[8];
+  double step_us[8];             /* time per MH step (us) of each helper candidate */
+} fmm_mc_tuning;
+
+/* Autotune the launch shapes for this chain's shape: the M2L output tile
+ * (96 or 192 coefficient rows per workgroup; both give identical results)
+ * is timed on the chain's data, and the number of helper workgroups of the
+ * whole-GPU run (mode 2) is timed over `steps` MH steps (0 = 1000) with
+ * inverse temperature beta and displacement half-width max_step, each
+ * candidate from the same clone of the chain's state, twice (the faster
+ * time counts); fewer helpers than accept blocks are chosen only when more
+ * than 2 % faster. Untuned shapes use 96 rows and one helper per block. The chain itself is
+ * not changed: the library allocates a temporary copy of the workspace for
+ * the trials and frees it before returning. The fastest choices apply to
+ * this handle and to every later fmm_mc_setup / fmm_mc_setup_batch of the
+ * same device, degree, depth and precision in this process. out (may be
+ * NULL) receives the measurements. */
+int fmm_mc_autotune(fmm_mc_t h, int64_t steps, double beta, double max_step, fmm_mc_tuning *out);
+
 /* Release the handle (not the caller's workspace). */
 int fmm_mc_destroy(fmm_mc_t h);
 

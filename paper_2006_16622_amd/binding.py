@@ -33,6 +33,13 @@ class RunOpts(ctypes.Structure):
                 ("trace_dE", ctypes.c_void_p), ("trace_acc", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("m2l_rows", ctypes.c_int32), ("helpers", ctypes.c_int32),
+                ("n_helper_candidates", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("m2l_ms", ctypes.c_double * 2), ("helper_candidates", ctypes.c_int32 * 8),
+                ("step_us", ctypes.c_double * 8)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64),
                 ("singular", ctypes.c_int64), ("dE_sum", ctypes.c_double),
@@ -67,6 +74,8 @@ SYMBOLS = {
     "fmm_mc_get_positions": (ctypes.c_int, [_vp, _dp]),
     "fmm_mc_dump_locals": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "fmm_mc_resetup": (ctypes.c_int, [_vp]),
+    "fmm_mc_autotune": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(Tuning)]),
     "fmm_mc_destroy": (ctypes.c_int, [_vp]),
     "fmm_mc_release_tables": (ctypes.c_int, []),
     "fmm_mc_last_timing": (ctypes.c_int, [_vp, _dp, ctypes.c_int]),
@@ -189,6 +198,15 @@ class Chain:
         out = np.zeros((8 ** (level - 1), C))
         _check(load_library().fmm_mc_dump_locals(self._h, int(level), _d(out)), "fmm_mc_dump_locals")
         return out
+
+    def autotune(self, steps: int = 1000, beta: float = 1.0, max_step: float = 0.0) -> dict:
+        """fmm_mc_autotune: pick the M2L tile and the helper count for this shape"""
+        t = Tuning()
+        _check(load_library().fmm_mc_autotune(self._h, int(steps), float(beta), float(max_step),
+                                              ctypes.byref(t)), "fmm_mc_autotune")
+        k = t.n_helper_candidates
+        return dict(m2l_rows=t.m2l_rows, helpers=t.helpers, m2l_ms=list(t.m2l_ms),
+                    helper_candidates=list(t.helper_candidates[:k]), step_us=list(t.step_us[:k]))
 
     def resetup(self):
         _check(load_library().fmm_mc_resetup(self._h), "fmm_mc_resetup")

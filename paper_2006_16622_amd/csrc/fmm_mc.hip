@@ -71,6 +71,14 @@ struct DevTables {
 std::mutex g_mu;
 std::vector<DevTables *> g_tables;
 
+// choices of the autotuner, per (device, p, depth, precision)
+struct TuneEntry {
+  int device, p, levels;
+  uint32_t mixed;
+  int m2l_rows, helpers;
+};
+std::vector<TuneEntry> g_tune;
+
 #define HIPCHK(x)                                  \
   do {                                             \
     hipError_t e_ = (x);                           \
@@ -284,6 +292,8 @@ struct fmm_mc_ctx {
   hipStream_t cap_stream = nullptr;   // private stream for graph capture
   hipGraph_t graph = nullptr;         // captured re-setup
   hipGraphExec_t gexec = nullptr;
+  int m2l_rows = 0;                   // tuned M2L output rows per workgroup (0: 96)
+  int helpers = 0;                    // tuned helper workgroups of the whole-GPU run (0: all blocks)
   double last_ms[4] = {0, 0, 0, 0};
   bool ready = false;
 };
@@ -316,9 +326,29 @@ struct SetupLaunch {
   const Tabs *tb = nullptr;
   bool restage = false;
   bool fp32_m2l = false;
+  int m2l_rows = 0;  // 96 or 192 (0: 96)
   int energy_mode = 2;
   hipEvent_t e1 = nullptr, e2 = nullptr;
 };
+
+void launch_m2l(const SetupLaunch &S) {
+  const Tabs &tb = *S.tb;
+  const bool narrow = S.m2l_rows ? S.m2l_rows == 96 : true;
+  const int TO = narrow ? 96 : 192;
+  dim3 mg(S.ntiles, (S.C + TO - 1) / TO);
+  hipStream_t st = S.st;
+  if (S.fp32_m2l) {
+    if (narrow)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<float, 96>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l32);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<float, 192>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l32);
+  } else {
+    if (narrow)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<double, 96>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<double, 192>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l);
+  }
+}
 
 int enqueue_setup(const SetupLaunch &S) {
   const Tabs &tb = *S.tb;
@@ -339,20 +369,7 @@ int enqueue_setup(const SetupLaunch &S) {
   for (int l = S.max_levels; l >= 1; --l)
     hipLaunchKernelGGL(k_m2m, dim3(1 << (3 * (l - 1)), nc), dim3(256), 0, st, S.chains, tb, l);
   if (S.e1) HIPCHK(hipEventRecord(S.e1, st));
-  const bool narrow = S.Cs <= 96;
-  const int TO = narrow ? 96 : 192;
-  dim3 mg(S.ntiles, (S.C + TO - 1) / TO);
-  if (S.fp32_m2l) {
-    if (narrow)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<float, 96>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l32);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<float, 192>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l32);
-  } else {
-    if (narrow)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<double, 96>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<double, 192>), mg, dim3(M2L_NT), 0, st, S.chains, tb, S.tiles, tb.m2l);
-  }
+  launch_m2l(S);
   if (S.e2) HIPCHK(hipEventRecord(S.e2, st));
   hipLaunchKernelGGL(k_lattice_init, dim3(1, nc), dim3(NT), 0, st, S.chains, tb);
   with_variant(variant_of(S.p), [&](auto gs, auto pm) {
@@ -380,6 +397,7 @@ SetupLaunch single_launch(fmm_mc_ctx *h) {
   S.Cs = h->Cs;
   S.tb = &h->tables->tabs;
   S.fp32_m2l = (h->flags & FMM_MC_MIXED) != 0;
+  S.m2l_rows = h->m2l_rows;
   return S;
 }
 
@@ -470,6 +488,14 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
   h->ws = (char *)dev_ws;
   h->ws_bytes = ws_bytes;
   h->ly = ly;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto &e : g_tune)
+      if (e.device == h->device && e.p == p && e.levels == levels && e.mixed == (flags & FMM_MC_MIXED)) {
+        h->m2l_rows = e.m2l_rows;
+        h->helpers = e.helpers;
+      }
+  }
   Chain &ch = h->ch;
   char *w = h->ws;
   ch.N = (int)n;
@@ -804,6 +830,7 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
     });
     RUNCHK(oe);
     int cap = std::max(1, ncu * std::max(per, 1));
+    if (h0->helpers > 0) G = std::min(G, h0->helpers + 1);
     G = std::max(1, std::min(G, std::min(cap, ncu)));
   }
   std::vector<int64_t> done(n_chains, 0);
@@ -1000,6 +1027,138 @@ int fmm_mc_dump_locals(fmm_mc_t h, int level, double *out) {
 int fmm_mc_last_timing(fmm_mc_t h, double *out, int nout) {
   if (!h || !out || nout < 1) return FMM_MC_EINVAL;
   for (int i = 0; i < nout && i < 4; ++i) out[i] = h->last_ms[i];
+  return FMM_MC_OK;
+}
+
+// a chain descriptor whose pointers are moved from one workspace to another
+extern "C++" {
+template <typename T>
+static T *rebase(T *p, const char *from, char *to) {
+  return p ? (T *)(to + ((const char *)p - from)) : nullptr;
+}
+
+static Chain rebase_chain(const Chain &c, const char *from, char *to) {
+  Chain r = c;
+  r.px = rebase(c.px, from, to);
+  r.py = rebase(c.py, from, to);
+  r.pz = rebase(c.pz, from, to);
+  r.pq = rebase(c.pq, from, to);
+  r.leaf_of = rebase(c.leaf_of, from, to);
+  r.slot_of = rebase(c.slot_of, from, to);
+  r.bin_cnt = rebase(c.bin_cnt, from, to);
+  r.bin_id = rebase(c.bin_id, from, to);
+  r.bin_p = rebase(c.bin_p, from, to);
+  r.Ld = rebase(c.Ld, from, to);
+  r.Mp = rebase(c.Mp, from, to);
+  r.K = rebase(c.K, from, to);
+  r.H = rebase(c.H, from, to);
+  r.dip = rebase(c.dip, from, to);
+  r.U = rebase(c.U, from, to);
+  r.status = rebase(c.status, from, to);
+  r.scratch = rebase(c.scratch, from, to);
+  r.mbox = rebase(c.mbox, from, to);
+  r.sync = rebase(c.sync, from, to);
+  r.red = rebase(c.red, from, to);
+  r.stage = rebase(c.stage, from, to);
+  return r;
+}
+}  // extern "C++"
+
+int fmm_mc_autotune(fmm_mc_t h, int64_t steps, double beta, double max_step, fmm_mc_tuning *out) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (steps < 0 || !(beta >= 0.0) || !std::isfinite(beta) || !(max_step >= 0.0) || !std::isfinite(max_step))
+    return FMM_MC_EINVAL;
+  if (steps == 0) steps = 1000;
+  const size_t bytes = h->ly.total;
+  char *tmp = nullptr;
+  HIPCHK(hipMalloc((void **)&tmp, bytes));
+  // a shadow context on a clone of the workspace (tables and events shared)
+  fmm_mc_ctx sh = *h;
+  sh.ws = tmp;
+  sh.graph = nullptr;
+  sh.gexec = nullptr;
+  sh.cap_stream = nullptr;
+  sh.ch = rebase_chain(h->ch, h->ws, tmp);
+  sh.d_chain = (Chain *)(tmp + h->ly.off[O_CHAIN]);
+  sh.d_tiles = (int4 *)(tmp + h->ly.off[O_TILES]);
+  auto clone = [&]() {
+    return hipMemcpyAsync(tmp, h->ws, bytes, hipMemcpyDeviceToDevice, h->stream) == hipSuccess &&
+           hipMemcpyAsync(sh.d_chain, &sh.ch, sizeof(Chain), hipMemcpyHostToDevice, h->stream) == hipSuccess;
+  };
+  fmm_mc_tuning t{};
+  int rc = clone() ? 0 : FMM_MC_EDEVICE;
+  // (a) M2L output rows per workgroup, timed on the clone (3 launches each)
+  const int rows[2] = {96, 192};
+  double best = 1e300;
+  t.m2l_rows = 192;
+  for (int k = 0; k < 2 && !rc; ++k) {
+    SetupLaunch S = single_launch(&sh);
+    S.m2l_rows = rows[k];
+    launch_m2l(S);
+    if (hipEventRecord(h->ev1, h->stream) != hipSuccess) rc = FMM_MC_EDEVICE;
+    for (int r = 0; r < 3; ++r) launch_m2l(S);
+    float ms = 0;
+    if (rc || hipEventRecord(h->ev2, h->stream) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess ||
+        hipEventElapsedTime(&ms, h->ev1, h->ev2) != hipSuccess)
+      rc = FMM_MC_EDEVICE;
+    t.m2l_ms[k] = ms / 3.0;
+    if (!rc && t.m2l_ms[k] < best) {
+      best = t.m2l_ms[k];
+      t.m2l_rows = rows[k];
+    }
+  }
+  // (b) helper workgroups of the whole-GPU run: `steps` MH steps of each
+  // candidate from the same cloned state, in two interleaved passes (the
+  // faster of the two counts); a smaller count than all blocks is taken
+  // only if it is more than 2 % faster
+  const int nblk = accept_blocks(h->ch.L, WG_SINGLE / h->GS);
+  const int div[8] = {1, 2, 3, 4, 6, 8, 12, 16};
+  for (int k = 0; k < 8; ++k) {
+    const int cand = (nblk + div[k] - 1) / div[k];
+    bool seen = false;
+    for (int j = 0; j < t.n_helper_candidates; ++j) seen = seen || t.helper_candidates[j] == cand;
+    if (seen || cand < 1) continue;
+    const int j = t.n_helper_candidates++;
+    t.helper_candidates[j] = cand;
+    t.step_us[j] = 1e300;
+  }
+  for (int pass = 0; pass < 2 && !rc; ++pass)
+    for (int j = 0; j < t.n_helper_candidates && !rc; ++j) {
+      if (!clone()) {
+        rc = FMM_MC_EDEVICE;
+        break;
+      }
+      sh.helpers = t.helper_candidates[j];
+      fmm_mc_t arr[1] = {&sh};
+      rc = run_chains(arr, 1, steps, 0x5eedULL, 0, beta, &max_step, 2, 0, nullptr, nullptr, nullptr, nullptr,
+                      nullptr, nullptr, nullptr, nullptr, nullptr);
+      t.step_us[j] = std::min(t.step_us[j], sh.last_ms[0] * 1e3 / (double)steps);
+    }
+  t.helpers = nblk;
+  best = t.step_us[0];  // candidate 0 is all blocks
+  for (int j = 1; j < t.n_helper_candidates; ++j)
+    if (t.step_us[j] < 0.98 * t.step_us[0] && t.step_us[j] < best) {
+      best = t.step_us[j];
+      t.helpers = t.helper_candidates[j];
+    }
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(tmp);
+  if (rc) return rc;
+  h->m2l_rows = t.m2l_rows;
+  h->helpers = t.helpers;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const uint32_t mixed = h->flags & FMM_MC_MIXED;
+    bool found = false;
+    for (auto &e : g_tune)
+      if (e.device == h->device && e.p == h->p && e.levels == h->levels && e.mixed == mixed) {
+        e.m2l_rows = t.m2l_rows;
+        e.helpers = t.helpers;
+        found = true;
+      }
+    if (!found) g_tune.push_back({h->device, h->p, h->levels, mixed, t.m2l_rows, t.helpers});
+  }
+  if (out) *out = t;
   return FMM_MC_OK;
 }
 

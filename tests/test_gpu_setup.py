@@ -138,3 +138,31 @@ def test_batched_run_with_periodic_resetup_matches_oracle():
         assert np.array_equal(tr["newpos"][k], ref["newpos"])
         rms = np.sqrt(np.mean(ref["dE"] ** 2))
         assert np.abs(tr["dE"][k] - ref["dE"]).max() <= 1e-10 * rms
+
+
+def test_autotune_keeps_state_and_results():
+    from paper_2006_16622_amd import Chain, run_chains
+    wl = W.uniform(3000, 3, 12, 0.04, seed=47, key=18)
+    a = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+    levels = range(2, wl.depth + 2)
+    before = {l: a.locals(l) for l in levels}
+    pos = a.positions()
+    t = a.autotune(steps=300, beta=wl.beta, max_step=wl.max_step)
+    say(f"[setup] autotune: {t}")
+    assert t["m2l_rows"] in (96, 192) and t["helpers"] >= 1 and len(t["step_us"]) >= 2
+    # the trials ran on a clone: the chain is unchanged
+    for l in levels:
+        assert np.array_equal(a.locals(l), before[l])
+    assert np.array_equal(a.positions(), pos)
+    # a new chain of this shape uses the tuned M2L tile: identical expansions
+    b = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+    for l in levels:
+        assert np.array_equal(b.locals(l), before[l])
+    # a run with the tuned helper count follows the oracle's trajectory
+    orc = O.Multilevel(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+    tr = orc.run(wl.seed, 0, 0, 150, wl.beta, wl.max_step)
+    st, gt = run_chains([b], 150, wl.seed, wl.beta, wl.max_step, mode=2, traces=True)
+    assert st[0]["status"] == 0
+    assert np.array_equal(gt["acc"][0], tr["acc"]) and np.array_equal(gt["newpos"][0], tr["newpos"])
+    rms = np.sqrt(np.mean(tr["dE"] ** 2))
+    assert np.abs(gt["dE"][0] - tr["dE"]).max() <= 1e-10 * rms
