@@ -71,6 +71,8 @@ struct Lds {
   static constexpr int NG = NT / GS;
   double *rec;                 // 3 Cs: recurrence constants
   float *rec32;                // 3 Cs: the same in FP32 (mixed precision evaluation)
+  int8_t *il_off;              // 8 * 189 * 3: interaction-list offsets per octant
+  double **dstp;               // NG: destination rows of an accept block's groups
   double *wl2p, *wdot, *sgnc;  // Cs each
   double *H, *K;               // Cs each: chain state
   double *st;                  // 8: dipole[3], running energy, setup energy
@@ -101,10 +103,12 @@ struct Lds {
     ints = (int *)(stash + 2);
     lat_col = ints + 384;
     rec32 = (float *)(lat_col + (size_t)ellw * Cs);
+    il_off = (int8_t *)(rec32 + 3 * (size_t)Cs);
+    dstp = (double **)(il_off + 8 * 189 * 3);
   }
-  static size_t bytes(int Cs, int ellw) {
+  __host__ __device__ static size_t bytes(int Cs, int ellw) {
     return sizeof(double) * ((size_t)(NG + 12 + ellw) * Cs + 8 + NT + 32 + 8) + 4 * (384 + (size_t)ellw * Cs) +
-           4 * 3 * (size_t)Cs;
+           4 * 3 * (size_t)Cs + 8 * 189 * 3 + sizeof(double *) * NG;
   }
   // recurrence constants in the evaluation type
   template <typename R>
@@ -117,6 +121,28 @@ struct Lds {
 };
 
 __device__ __forceinline__ int cslot(int n, int m) { return n * n + n + m; }
+
+// Global-memory view of a workspace pointer. The chain's pointers reach the
+// kernels through LDS, so the compiler no longer knows they address global
+// memory and would use flat instructions, which also count against the LDS
+// counter: every wait for an LDS result would then wait for all pending
+// global stores too. Accesses through glb() are global instructions.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(T *p) {
+  return (gptr<T>)p;
+}
+
+// bin records (x, y, z, q) through the global view
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double4 ld_rec(const double4 *p, size_t i) {
+  const dvec4 v = glb((const dvec4 *)p)[i];
+  return make_double4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st_rec(double4 *p, size_t i, const double4 &r) {
+  glb((dvec4 *)p)[i] = (dvec4){r.x, r.y, r.z, r.w};
+}
 
 // ------------------------------------------------------------------ rounding
 // Wrap into [0, a): x - a floor(x/a), a result equal to a (or below 0 by
@@ -245,8 +271,8 @@ __device__ __forceinline__ float sqrt_r(float v) { return sqrtf(v); }
 // R is the arithmetic type of the evaluation (double, or float in the mixed
 // precision mode); the results are stored as doubles.
 template <int GS, int PMAX, int KIND, bool ACC, typename R = double>
-__device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const R *rec, R x, R y, R z, R c,
-                                                double *buf) {
+__device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const R *__restrict__ rec, R x, R y, R z,
+                                                R c, double *__restrict__ buf) {
   const int p = tb.p, Cs = tb.Cs;
   const int m = lane;
   const R r2 = x * x + y * y + z * z;

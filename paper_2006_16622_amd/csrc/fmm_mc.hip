@@ -757,7 +757,7 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   const int GS = h0->GS;
   const bool single = (n_chains == 1 && mode != 1);
   const int NT = single ? WG_SINGLE : WG_BATCH;
-  const size_t shm = smem_bytes(GS, tb, NT);
+  size_t shm = smem_bytes(GS, tb, NT);
   // launch arguments in stream-ordered device memory, freed at the end
   double *d_step = nullptr, *d_stats = nullptr;
   Chain *d_chains = nullptr;
@@ -819,19 +819,34 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   rp.stats = d_stats;
   int G = 1;
   if (single) {
+    // workgroup 0 proposes, the others (one per CU at most) hold the accept
+    // blocks; the busiest helper's speculative rows must fit its LDS
     const int NG = NT / GS;
-    G = accept_blocks(h0->ch.L, NG) + 1;  // workgroup 0 proposes, the others update
-    int ncu = 0, per = 0;
+    const int nblk = accept_blocks(h0->ch.L, NG);
+    int ncu = 0, maxlds = 0, per = 0;
     RUNCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
+    RUNCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, h0->device));
+    auto kmax_of = [&](int g) { return g < 2 ? 1 : (nblk + g - 2) / (g - 1); };
+    auto shm_of = [&](int g) { return smem_bytes(GS, tb, NT) + (g < 2 ? 0 : spec_extra_bytes(kmax_of(g), NG, h0->Cs)); };
+    G = nblk + 1;
+    if (h0->helpers > 0) G = std::min(G, h0->helpers + 1);
+    G = std::max(1, std::min(G, ncu));
+    while (G < ncu && G < nblk + 1 && (kmax_of(G) > SPEC_MAX || shm_of(G) > (size_t)maxlds)) ++G;
+    if (kmax_of(G) > SPEC_MAX || shm_of(G) > (size_t)maxlds) {
+      release();
+      return FMM_MC_EDEVICE;
+    }
+    shm = shm_of(G);
     hipError_t oe = hipSuccess;
     with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
       oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &per, k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>, NT, shm);
     });
     RUNCHK(oe);
-    int cap = std::max(1, ncu * std::max(per, 1));
-    if (h0->helpers > 0) G = std::min(G, h0->helpers + 1);
-    G = std::max(1, std::min(G, std::min(cap, ncu)));
+    if (per < 1) {
+      release();
+      return FMM_MC_EDEVICE;
+    }
   }
   std::vector<int64_t> done(n_chains, 0);
   std::vector<double> acc(8 * n_chains, 0.0);  // accumulated stats per chain

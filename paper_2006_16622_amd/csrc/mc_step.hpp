@@ -56,6 +56,7 @@ __device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<G
     sm.rec[i] = tb.rec[i];
     sm.rec32[i] = (float)tb.rec[i];
   }
+  for (int i = threadIdx.x; i < 8 * 189 * 3; i += NT) sm.il_off[i] = tb.il_off[i];
   for (int i = threadIdx.x; i < Cs; i += NT) {
     sm.wl2p[i] = tb.wl2p[i];
     sm.wdot[i] = tb.wdot[i];
@@ -108,11 +109,16 @@ struct ProposeOut {
 //      - (2 pi/3V)(|D + q(r'-r)|^2 - |D|^2)                            (tin-foil)
 // The new-side direct sum leaves out every image of the moving charge in
 // the near region together with the matching self term (they cancel). The
-// bin records the bookkeeping of an accept needs are kept in LDS. `spare`
-// is run by the last wavefront while the others evaluate the expansions.
-template <int GS, int PM, typename R, int NT, typename Spare>
+// bin records the bookkeeping of an accept needs are kept in LDS. `early`
+// is run by the last wavefront at the start, `spare` by the last wavefront
+// while the others evaluate the expansions.
+struct NoWork {
+  __device__ void operator()(int) const {}
+};
+
+template <int GS, int PM, typename R, int NT, typename Spare, typename Early = NoWork>
 __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm,
-                                 Spare &&spare) {
+                                 Spare &&spare, Early &&early = NoWork{}) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   const int Cs = tb.Cs, C = tb.C;
@@ -122,6 +128,22 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
   const int L = ch.L, d = ch.d, B = ch.B;
   const int npts = 2 * d + 2;
   const int nL = 1 << (L - 1);
+
+  if (t >= NT - 64) early(t - (NT - 64));
+
+  // ---- the first round of level coefficients is requested before the near
+  // field, so that its memory latency overlaps the direct sum
+  double lv0[NJ];
+  if (g >= 2 && g < npts) {
+    const int l = 2 + (g - 2) / 2, side = (g - 2) % 2, n = 1 << (l - 1);
+    const int *c = side ? mv.c1[l] : mv.c0[l];
+    const auto src = glb(ch.Ld) + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      int s = lane + j * GS;
+      lv0[j] = s < C ? src[s] : 0.0;
+    }
+  }
 
   // ---- near field: 4 threads per near cell, first slot loaded with the count
   double dold = 0.0, dnew = 0.0;
@@ -137,15 +159,15 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     const int w = (fx + 1) + 3 * (fy + 1) + 9 * (fz + 1);
     const double sx = fx * a, sy = fy * a, sz = fz * a;
     const size_t base = (size_t)cell * B;
-    const int cnt = ch.bin_cnt[cell];
-    int id = ch.bin_id[base + j0];
-    double4 pj = ch.bin_p[base + j0];
+    const int cnt = glb(ch.bin_cnt)[cell];
+    int id = glb(ch.bin_id)[base + j0];
+    double4 pj = ld_rec(ch.bin_p, base + j0);
     if (ee == 13 && j0 == 0) ints[side ? I_CNTNEW : I_CNTOLD] = cnt;
     const double *x = side ? mv.rn : mv.r;
     for (int j = j0; j < cnt; j += 4) {
       if (j != j0) {
-        id = ch.bin_id[base + j];
-        pj = ch.bin_p[base + j];
+        id = glb(ch.bin_id)[base + j];
+        pj = ld_rec(ch.bin_p, base + j);
       }
       if (side == 0 && ee == 13) {  // the moving charge's own leaf bin
         if (id == mv.idx) ints[I_SLOTK] = j;
@@ -196,10 +218,22 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
       }
       // the expansion coefficients are loaded while the harmonics are formed
       double lv[NJ];
+      if (base == 0 && pt >= 2) {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        int s = lane + j * GS;
-        lv[j] = s < C ? src[s] : 0.0;
+        for (int j = 0; j < NJ; ++j) lv[j] = lv0[j];
+      } else if (pt < 2) {  // the lattice vector H, in LDS
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          int s = lane + j * GS;
+          lv[j] = s < C ? src[s] : 0.0;
+        }
+      } else {
+        const auto gsrc = glb(src);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          int s = lane + j * GS;
+          lv[j] = s < C ? gsrc[s] : 0.0;
+        }
       }
       if (pt < 2)  // the periodic lattice term stays in FP64
         group_harmonics<GS, PM, 0, false>(lane, tb, sm.rec, x[0], x[1], x[2], 1.0, buf);
@@ -302,7 +336,8 @@ struct FineItem {
   double q0, q1;
 };
 
-__device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, const Move &mv, int l, int item) {
+__device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, const int8_t *il_off, const Move &mv,
+                                              int l, int item) {
   FineItem it;
   it.active = 0;
   it.two = 0;
@@ -312,7 +347,7 @@ __device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, c
   const int *c = side ? mv.c1[l] : mv.c0[l];
   const int *co = side ? mv.c0[l] : mv.c1[l];
   const int oc = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
-  const int8_t *o = tb.il_off + (oc * 189 + k189) * 3;
+  const int8_t *o = il_off + (oc * 189 + k189) * 3;
   int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
   int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
   int b_other[3];
@@ -379,13 +414,21 @@ __device__ __forceinline__ void coarse_contrib(const Tabs &tb, const R *rec, con
   group_harmonics<GS, PM, 2, true, R>(lane, tb, rec, (R)v[0], (R)v[1], (R)v[2], (R)(side ? mv.q : -mv.q), buf);
 }
 
+// The updated target rows of accept block blk of move mv, formed in LDS
+// without writing the targets: out (NG x Cs doubles) receives the old
+// values read now plus the block's additions, and dst[g] the row that
+// group g's result replaces (null: none). A coarse block (level 2 or 3)
+// sums its groups' partial contributions in out itself and forms one row,
+// in out[0..C), for dst[0]. The arithmetic and its order are those of an
+// immediate update. Returns whether the block is coarse.
 template <int GS, int PM, typename R, int NT>
-__device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS, NT> &sm) {
+__device__ bool accept_block_compute(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS, NT> &sm,
+                                     double *out, double **dst) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   const int Cs = tb.Cs, C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
-  double *acc = sm.gbuf;  // NG * Cs
+  double *acc = out;  // NG * Cs partial sums of a coarse block
   int *lst = sm.ints + I_LIST;
   const double a = ch.a, q = mv.q;
   const int L = ch.L;
@@ -403,8 +446,9 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
     const int l = coarse_l, n = 1 << (l - 1);
     const double h = a / n;
     int s[3] = {s_lin % n, (s_lin / n) % n, s_lin / (n * n)};
-    double *dst = ch.Ld + ch.ld_off[l] + (size_t)s_lin * Cs;
-    double old = t < C ? dst[t] : 0.0;  // C <= NT for the 16-lane groups
+    double *row = ch.Ld + ch.ld_off[l] + (size_t)s_lin * Cs;
+    double old = t < C ? glb(row)[t] : 0.0;  // C <= NT for the 16-lane groups
+    if (t < NG) dst[t] = t == 0 ? row : nullptr;
     if (t < 64) {
       bool valid = false;
       int side = t / 27, e = t % 27;
@@ -440,49 +484,78 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
       const double *x = side ? mv.rn : mv.r;
       double v[3];
       for (int k = 0; k < 3; ++k) v[k] = (x[k] - ((s[k] + n * w[k]) + 0.5) * h) / h;
-      group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)v[0], (R)v[1], (R)v[2], (R)(side ? q : -q),
-                                       acc + (size_t)g * Cs);
+      group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)v[0], (R)v[1], (R)v[2],
+                                          (R)(side ? q : -q), acc + (size_t)g * Cs);
     }
     __syncthreads();
     for (int k = t; k < C; k += NT) {
       double sum = 0.0;
       for (int gg = 0; gg < NG; ++gg) sum += acc[(size_t)gg * Cs + k];
-      dst[k] = (k == t ? old : dst[k]) + sum;
+      out[k] = (k == t ? old : glb(row)[k]) + sum;
     }
-    __syncthreads();
-    return;
+    return true;
   }
   // ---- fine levels: item = (level, side, IL offset)
   int b2 = blk - 72;
   const int bpl = (378 + NG - 1) / NG;
   const int l = 4 + b2 / bpl;
   const int item = (b2 % bpl) * NG + g;
-  if (l <= L && item < 378) {
-    FineItem it = fine_item(ch, tb, mv, l, item);
-    if (!it.active) return;
-    double *buf = acc + (size_t)g * Cs;
-    // the target's coefficients are loaded while the harmonics are formed
-    double old[NJ];
+  FineItem it;
+  it.active = 0;
+  if (l <= L && item < 378) it = fine_item(ch, tb, sm.il_off, mv, l, item);
+  if (lane == 0) dst[g] = it.active ? it.dst : nullptr;
+  if (!it.active) return false;
+  double *buf = out + (size_t)g * Cs;
+  // the target's coefficients are loaded while the harmonics are formed
+  double old[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      int k = lane + j * GS;
-      old[j] = k < C ? it.dst[k] : 0.0;
-    }
-    group_harmonics<GS, PM, 2, false, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
-                                         (R)it.q0, buf);
-    if (it.two) {
-      __builtin_amdgcn_wave_barrier();
-      group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)it.v1[0], (R)it.v1[1],
-                                          (R)it.v1[2], (R)it.q1, buf);
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      int k = lane + j * GS;
-      if (k < C) it.dst[k] = old[j] + buf[k];
-    }
+  for (int j = 0; j < NJ; ++j) {
+    int k = lane + j * GS;
+    old[j] = k < C ? glb(it.dst)[k] : 0.0;
   }
+  group_harmonics<GS, PM, 2, false, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
+                                       (R)it.q0, buf);
+  if (it.two) {
+    __builtin_amdgcn_wave_barrier();
+    group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)it.v1[0], (R)it.v1[1], (R)it.v1[2],
+                                        (R)it.q1, buf);
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    int k = lane + j * GS;
+    if (k < C) buf[k] = old[j] + buf[k];
+  }
+  return false;
+}
+
+// write the rows formed by accept_block_compute (all threads; the caller
+// synchronises the workgroup between the two)
+template <int GS, int NT>
+__device__ __forceinline__ void accept_block_store(const Tabs &tb, bool coarse, const double *out,
+                                                   double *const *dst) {
+  const int C = tb.C, Cs = tb.Cs, t = threadIdx.x;
+  if (coarse) {
+    const auto row = glb(dst[0]);
+    for (int k = t; k < C; k += NT) row[k] = out[k];
+    return;
+  }
+  const int g = t / GS, lane = t % GS;
+  if (dst[g]) {
+    const auto row = glb(dst[g]);
+    for (int k = lane; k < C; k += GS) row[k] = out[(size_t)g * Cs + k];
+  }
+}
+
+// the update of accept block blk, applied at once
+template <int GS, int PM, typename R, int NT>
+__device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS, NT> &sm) {
+  double **dst = sm.dstp;
+  bool coarse = accept_block_compute<GS, PM, R>(ch, tb, mv, blk, sm, sm.gbuf, dst);
+  __syncthreads();
+  accept_block_store<GS, NT>(tb, coarse, sm.gbuf, dst);
+  __syncthreads();
 }
 
 // The whole update of an accepted move by one workgroup (one chain per
@@ -521,7 +594,7 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
     const int cell = i / C, k = i % C;
     double sum = 0.0;
     for (int part = 0; part < SPLIT2; ++part) sum += sm.gbuf[(size_t)(cell + 8 * part) * Cs + k];
-    double *dst = ch.Ld + ch.ld_off[2] + (size_t)cell * Cs;
+    const auto dst = glb(ch.Ld) + ch.ld_off[2] + (size_t)cell * Cs;
     dst[k] += sum;
   }
   __syncthreads();
@@ -529,7 +602,7 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
   if (L >= 3) {
     for (int cell = g; cell < 64; cell += NG) {
       const int s3[3] = {cell % 4, (cell / 4) % 4, cell / 16};
-      double *dst = ch.Ld + ch.ld_off[3] + (size_t)cell * Cs;
+      const auto dst = glb(ch.Ld) + ch.ld_off[3] + (size_t)cell * Cs;
       double old[NJ];
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -557,13 +630,13 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
   // ---- levels >= 4: each item's target is loaded while its harmonics are formed
   const int nfine = L >= 4 ? (L - 3) * 378 : 0;
   for (int i = g; i < nfine; i += NG) {
-    FineItem it = fine_item(ch, tb, mv, 4 + i / 378, i % 378);
+    FineItem it = fine_item(ch, tb, sm.il_off, mv, 4 + i / 378, i % 378);
     if (!it.active) continue;
     double old[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       int k = lane + j * GS;
-      old[j] = k < C ? it.dst[k] : 0.0;
+      old[j] = k < C ? glb(it.dst)[k] : 0.0;
     }
     group_harmonics<GS, PM, 2, false, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
                                          (R)it.q0, buf);
@@ -577,7 +650,7 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       int k = lane + j * GS;
-      if (k < C) it.dst[k] = old[j] + buf[k];
+      if (k < C) glb(it.dst)[k] = old[j] + buf[k];
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -609,7 +682,7 @@ __device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &m
     const int sl = ints[I_SLOTK];
     const double4 rec = make_double4(mv.rn[0], mv.rn[1], mv.rn[2], q);
     if (oldc == newc) {
-      ch.bin_p[(size_t)oldc * B + sl] = rec;
+      st_rec(ch.bin_p, (size_t)oldc * B + sl, rec);
     } else {
       const int cnt = ints[I_CNTNEW];
       if (cnt >= B) {
@@ -618,22 +691,22 @@ __device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &m
         const int last = ints[I_CNTOLD] - 1;
         if (sl != last) {
           const int moved = ints[I_IDLAST];
-          ch.bin_id[(size_t)oldc * B + sl] = moved;
-          ch.bin_p[(size_t)oldc * B + sl] = sm.stash[0];
-          ch.slot_of[moved] = sl;
+          glb(ch.bin_id)[(size_t)oldc * B + sl] = moved;
+          st_rec(ch.bin_p, (size_t)oldc * B + sl, sm.stash[0]);
+          glb(ch.slot_of)[moved] = sl;
         }
-        ch.bin_cnt[oldc] = last;
-        ch.bin_id[(size_t)newc * B + cnt] = k;
-        ch.bin_p[(size_t)newc * B + cnt] = rec;
-        ch.bin_cnt[newc] = cnt + 1;
-        ch.slot_of[k] = cnt;
-        ch.leaf_of[k] = newc;
+        glb(ch.bin_cnt)[oldc] = last;
+        glb(ch.bin_id)[(size_t)newc * B + cnt] = k;
+        st_rec(ch.bin_p, (size_t)newc * B + cnt, rec);
+        glb(ch.bin_cnt)[newc] = cnt + 1;
+        glb(ch.slot_of)[k] = cnt;
+        glb(ch.leaf_of)[k] = newc;
       }
     }
     if (!ovf) {
-      ch.px[k] = mv.rn[0];
-      ch.py[k] = mv.rn[1];
-      ch.pz[k] = mv.rn[2];
+      glb(ch.px)[k] = mv.rn[0];
+      glb(ch.py)[k] = mv.rn[1];
+      glb(ch.pz)[k] = mv.rn[2];
       for (int j = 0; j < 3; ++j) sm.st[j] += q * (mv.rn[j] - mv.r[j]);
       sm.st[3] += dE;
     }
@@ -661,12 +734,12 @@ __device__ void load_bin_records(const Chain &ch, const Move &mv, Lds<GS, NT> &s
     const int oldc = lin3(n, mv.c0[L][0], mv.c0[L][1], mv.c0[L][2]);
     const int newc = lin3(n, mv.c1[L][0], mv.c1[L][1], mv.c1[L][2]);
     int *ints = sm.ints;
-    ints[I_SLOTK] = ch.slot_of[mv.idx];
-    ints[I_CNTOLD] = ch.bin_cnt[oldc];
-    ints[I_CNTNEW] = ch.bin_cnt[newc];
+    ints[I_SLOTK] = glb(ch.slot_of)[mv.idx];
+    ints[I_CNTOLD] = glb(ch.bin_cnt)[oldc];
+    ints[I_CNTNEW] = glb(ch.bin_cnt)[newc];
     int last = ints[I_CNTOLD] - 1;
-    ints[I_IDLAST] = ch.bin_id[(size_t)oldc * B + last];
-    sm.stash[0] = ch.bin_p[(size_t)oldc * B + last];
+    ints[I_IDLAST] = glb(ch.bin_id)[(size_t)oldc * B + last];
+    sm.stash[0] = ld_rec(ch.bin_p, (size_t)oldc * B + last);
   }
 }
 

@@ -67,10 +67,10 @@ __device__ __forceinline__ void draw_into(const RunParams &rp, int c, int64_t t,
   } else {
     mh_draw(rp.seed, (uint64_t)c, (uint64_t)(rp.t0 + t), ch.N, D, nd.idx, nd.d, nd.u);
   }
-  nd.r[0] = ch.px[nd.idx];
-  nd.r[1] = ch.py[nd.idx];
-  nd.r[2] = ch.pz[nd.idx];
-  nd.q = ch.pq[nd.idx];
+  nd.r[0] = glb(ch.px)[nd.idx];
+  nd.r[1] = glb(ch.py)[nd.idx];
+  nd.r[2] = glb(ch.pz)[nd.idx];
+  nd.q = glb(ch.pq)[nd.idx];
 }
 
 // Build the move of a step from its draw (thread 0). If the previous step
@@ -141,14 +141,14 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
       nprop += 1;
       nsing += po.singular;
       int64_t o = (int64_t)c * rp.steps + step;
-      if (rp.tr_idx) rp.tr_idx[o] = mv.idx;
+      if (rp.tr_idx) glb(rp.tr_idx)[o] = mv.idx;
       if (rp.tr_pos)
-        for (int k = 0; k < 3; ++k) rp.tr_pos[3 * o + k] = mv.rn[k];
-      if (rp.tr_dE) rp.tr_dE[o] = po.dE;
-      if (rp.tr_acc) rp.tr_acc[o] = (uint8_t)acc;
+        for (int k = 0; k < 3; ++k) glb(rp.tr_pos)[3 * o + k] = mv.rn[k];
+      if (rp.tr_dE) glb(rp.tr_dE)[o] = po.dE;
+      if (rp.tr_acc) glb(rp.tr_acc)[o] = (uint8_t)acc;
       if (rp.tr_leaf) {
         int n = 1 << (ch.L - 1);
-        rp.tr_leaf[o] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
+        glb(rp.tr_leaf)[o] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
       }
     }
     __syncthreads();
@@ -189,10 +189,13 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
 // Polling uses relaxed agent-scope loads (no cache invalidation per poll);
 // the caller issues one acquire fence after the awaited value is seen.
 __device__ __forceinline__ unsigned ld_relaxed(unsigned *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(glb(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_release(unsigned *p, unsigned v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(glb(p), v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(unsigned *p, unsigned v) {
+  __hip_atomic_store(glb(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // bounded spin: returns false after `limit` ticks of the 100 MHz clock
@@ -220,7 +223,29 @@ __device__ __forceinline__ bool spin_all_equal(unsigned *flags, int G, unsigned 
 }
 
 constexpr uint64_t SPIN_LIMIT = 100000000ull * 20;  // 20 s of the 100 MHz clock
+constexpr int SPEC_MAX = 8;  // accept blocks one helper of the whole-GPU run can hold
 
+// dynamic LDS a helper of the whole-GPU run needs beyond the standard
+// layout when the busiest helper holds k accept blocks
+__host__ __device__ inline size_t spec_extra_bytes(int k, int NG, int Cs) {
+  return (size_t)(k - 1) * NG * Cs * sizeof(double) + (size_t)k * NG * sizeof(double *);
+}
+
+// Protocol of the whole-GPU chain (sync words of the workspace):
+//   sync[0] mvseq   number of the latest posted move (1, 2, ... per launch)
+//   sync[1] dec     2 * number + accepted, once that move is decided
+//   sync[2] stop, sync[3] error, sync[64 + w] done flag of helper w
+//   mailbox         two slots of 8 doubles (idx, q, r, r'), slot = number & 1
+// Workgroup 0 posts each move early in its proposal. While it proposes, every
+// helper reads the move (validated like a seqlock: a slot is only rewritten
+// two moves later), locates it and forms, in LDS, the updated rows of its
+// accept blocks without writing them (speculation). When the decision says
+// accepted, the helpers store those rows and raise their done flags;
+// workgroup 0 does its bookkeeping meanwhile and waits for all flags before
+// the next proposal reads any expansion. A rejected move's rows are
+// dropped. A helper never misses an accepted move: workgroup 0 posts the
+// next move only after every helper has finished it. Every wait is
+// bounded; on time-out the chain stops with an error status.
 template <int GS, int PM, typename R>
 __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb, RunParams rp) {
   constexpr int NT = WG_SINGLE;
@@ -229,6 +254,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   __shared__ Move mv;
   __shared__ NextDraw nd;
   __shared__ int s_flag, s_acc;
+  __shared__ unsigned s_seq;
   __shared__ double s_u;
   __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
   const int t = threadIdx.x, w = blockIdx.x, G = gridDim.x;
@@ -236,7 +262,8 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   __syncthreads();
   const Chain &ch = chl;
   const int nblk = accept_blocks(ch.L, NG);
-  unsigned *seq = ch.sync, *stop = ch.sync + 2, *err = ch.sync + 3, *doneflag = ch.sync + 64;
+  unsigned *mvseq = ch.sync, *dec = ch.sync + 1, *stop = ch.sync + 2, *err = ch.sync + 3;
+  unsigned *doneflag = ch.sync + 64;
   double *mb = ch.mbox;
   Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, w == 0);
@@ -246,7 +273,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     const double D = rp.max_step[c];
     double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
     int status = 0;
-    unsigned myseq = 0;
+    unsigned num = 0;  // move number of this launch
     uint64_t tick_prop = 0, tick_acc = 0, tick_wait = 0;
     bool prev_acc = false;
     int prev_idx = -1;
@@ -257,6 +284,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     __syncthreads();
     for (int64_t step = s0; step < rp.steps; ++step) {
       uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
+      ++num;  // every thread keeps the move number
       if (t == 0) {
         move_from_draw(rp, ch, nd, prev_acc, prev_idx, prev_rn, mv);
         s_u = nd.u;
@@ -265,33 +293,44 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       locate_move_par(ch, mv);
       __syncthreads();
       const double u = s_u;
-      ProposeOut po = propose_wg<GS, PM, R>(ch, tb, mv, sm, [&](int lane) {
-        if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
-      });
+      // the last wavefront of the proposal posts the move to the helpers
+      // first (its release fence is hidden behind the near field and the
+      // expansion evaluations) and later fetches the next draw
+      ProposeOut po = propose_wg<GS, PM, R>(
+          ch, tb, mv, sm,
+          [&](int lane) {
+            if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
+          },
+          [&](int lane) {
+            if (lane == 0 && G > 1) {
+              const auto slot = glb(mb) + 8 * (num & 1);
+              slot[0] = (double)mv.idx;
+              slot[1] = mv.q;
+              for (int k = 0; k < 3; ++k) {
+                slot[2 + k] = mv.r[k];
+                slot[5 + k] = mv.rn[k];
+              }
+              st_release(mvseq, num);
+            }
+          });
       uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
       tick_prop += t_1 - t_0;
       if (t == 0) {
         int acc = !po.singular && (u < exp(-rp.beta * po.dE));
         s_acc = acc;
+        // the decision publishes no data: a relaxed store
+        if (G > 1) st_relaxed(dec, 2u * num + (unsigned)acc);
         nprop += 1;
         nsing += po.singular;
         const int64_t o = (int64_t)c * rp.steps + step;
-        if (rp.tr_idx) rp.tr_idx[o] = mv.idx;
+        if (rp.tr_idx) glb(rp.tr_idx)[o] = mv.idx;
         if (rp.tr_pos)
-          for (int k = 0; k < 3; ++k) rp.tr_pos[3 * o + k] = mv.rn[k];
-        if (rp.tr_dE) rp.tr_dE[o] = po.dE;
-        if (rp.tr_acc) rp.tr_acc[o] = (uint8_t)acc;
+          for (int k = 0; k < 3; ++k) glb(rp.tr_pos)[3 * o + k] = mv.rn[k];
+        if (rp.tr_dE) glb(rp.tr_dE)[o] = po.dE;
+        if (rp.tr_acc) glb(rp.tr_acc)[o] = (uint8_t)acc;
         if (rp.tr_leaf) {
           int n = 1 << (ch.L - 1);
-          rp.tr_leaf[o] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
-        }
-        if (acc && G > 1) {
-          mb[0] = (double)mv.idx;
-          mb[1] = mv.q;
-          for (int k = 0; k < 3; ++k) {
-            mb[2 + k] = mv.r[k];
-            mb[5 + k] = mv.rn[k];
-          }
+          glb(rp.tr_leaf)[o] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
         }
       }
       __syncthreads();
@@ -299,15 +338,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       prev_idx = mv.idx;
       for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
       if (prev_acc) {
-        if (G > 1) {
-          ++myseq;  // every thread keeps the sequence number (wavefront 0 waits on it)
-          if (t == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            st_release(seq, myseq);
-          }
-        } else {
-          accept_all_wg<GS, PM, R>(ch, tb, mv, sm);
-        }
+        if (G == 1) accept_all_wg<GS, PM, R>(ch, tb, mv, sm);
         int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, po.dE, sm);
         if (t == 0) {
           nacc += 1;
@@ -317,7 +348,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
         tick_acc += t_2 - t_1;
         if (G > 1) {
           if (t < 64) {
-            bool ok = spin_all_equal(doneflag, G, myseq, SPIN_LIMIT);
+            bool ok = spin_all_equal(doneflag, G, num, SPIN_LIMIT);
             if (t == 0) s_flag = ok ? 0 : 1;
           }
           __syncthreads();
@@ -337,61 +368,115 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     }
     if (G > 1 && t == 0) {
       st_release(stop, 1u);
-      st_release(seq, ++myseq);
+      st_release(mvseq, num + 1);
     }
     __syncthreads();
     writeback_lds(ch, tb, sm);
     if (t == 0) {
-      rp.stats[0] = nprop;
-      rp.stats[1] = nacc;
-      rp.stats[2] = nsing;
-      rp.stats[3] = dEsum;
-      rp.stats[4] = status;
-      rp.stats[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
-      rp.stats[6] = tick_acc * 0.01;
-      rp.stats[7] = tick_wait * 0.01;
+      glb(rp.stats)[0] = nprop;
+      glb(rp.stats)[1] = nacc;
+      glb(rp.stats)[2] = nsing;
+      glb(rp.stats)[3] = dEsum;
+      glb(rp.stats)[4] = status;
+      glb(rp.stats)[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
+      glb(rp.stats)[6] = tick_acc * 0.01;
+      glb(rp.stats)[7] = tick_wait * 0.01;
     }
     return;
   }
-  // helper workgroups: wait for a posted move, do their share of the blocks
-  unsigned myseq = 0;
+  // ---- helper workgroups: block k of this helper (blocks w-1, w-1+G-1, ...)
+  // forms its rows in spec(k): the group buffers for k = 0, then the dynamic
+  // LDS after the standard layout; then the row pointers of all its blocks
+  const int kmax = (nblk + G - 2) / (G - 1);  // blocks of the busiest helper
+  double *xbuf = lds + Lds<GS, NT>::bytes(tb.Cs, tb.lat_lds ? tb.lat_w : 0) / sizeof(double);
+  double **sdst = (double **)(xbuf + (size_t)(kmax - 1) * NG * tb.Cs);
+  auto spec = [&](int k) { return k == 0 ? sm.gbuf : xbuf + (size_t)(k - 1) * NG * tb.Cs; };
+  __shared__ bool s_coarse[SPEC_MAX];
+  unsigned cur = 0;  // latest move number seen
   while (true) {
+    // a move newer than `cur`
     if (t == 0) {
       unsigned v;
-      bool ok = spin_until_ne(seq, myseq, v, SPIN_LIMIT);
+      bool ok = spin_until_ne(mvseq, cur, v, SPIN_LIMIT);
       s_flag = ok ? 0 : 1;
       if (ok) {
-        myseq = v;
-        if (__hip_atomic_load(stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) s_flag = 2;
+        s_seq = v;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the stop flag is stored before the number
+        if (__hip_atomic_load(glb(stop), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) s_flag = 2;
       }
     }
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    int f = s_flag;
+    const int f = s_flag;
+    const unsigned num = s_seq;
     __syncthreads();
     if (f == 1) {
-      if (t == 0) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t == 0) st_relaxed(err, 1u);
       return;
     }
     if (f == 2) return;
+    cur = num;
+    // read the move. Its slot is rewritten two moves later; a helper can
+    // still be reading it then only if this move and the next were both
+    // rejected (an accepted move holds workgroup 0 until every helper has
+    // finished it), so a mixed read only ever feeds rows that are dropped.
     if (t == 0) {
-      mv.idx = (int)mb[0];
-      mv.q = mb[1];
+      const auto slot = glb(mb) + 8 * (num & 1);
+      double m[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) m[k] = slot[k];
+      mv.idx = (int)m[0];
+      mv.q = m[1];
       for (int k = 0; k < 3; ++k) {
-        mv.r[k] = mb[2 + k];
-        mv.rn[k] = mb[5 + k];
+        mv.r[k] = m[2 + k];
+        mv.rn[k] = m[5 + k];
       }
     }
     __syncthreads();
     locate_move_par(ch, mv);
     __syncthreads();
-    for (int b = w - 1; b < nblk; b += G - 1) {
-      accept_block<GS, PM, R>(ch, tb, mv, b, sm);
+    // speculation: the updated rows of every own block, in LDS
+    for (int k = 0, b = w - 1; b < nblk; ++k, b += G - 1) {
+      bool coarse = accept_block_compute<GS, PM, R>(ch, tb, mv, b, sm, spec(k), sdst + (size_t)k * NG);
+      if (t == 0) s_coarse[k] = coarse;
       __syncthreads();
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // the decision of this move (or a newer move, which means rejected)
+    if (t == 0) {
+      uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      int res = 0;  // 0 rejected, 1 accepted, 2 time-out
+      while (true) {
+        const unsigned d = ld_relaxed(dec);
+        if ((d >> 1) == num) {
+          res = (int)(d & 1u);
+          break;
+        }
+        if ((d >> 1) > num || ld_relaxed(mvseq) != num) break;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > SPIN_LIMIT) {
+          res = 2;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      s_flag = res;
+    }
     __syncthreads();
-    if (t == 0) st_release(&doneflag[w], myseq);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int res = s_flag;
+    __syncthreads();
+    if (res == 2) {
+      if (t == 0) st_relaxed(err, 1u);
+      return;
+    }
+    if (res == 1) {
+      for (int k = 0, b = w - 1; b < nblk; ++k, b += G - 1)
+        accept_block_store<GS, NT>(tb, s_coarse[k], spec(k), sdst + (size_t)k * NG);
+      // every thread's rows are released by its own fence; after the
+      // barrier the flag itself needs no second release
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (t == 0) st_relaxed(&doneflag[w], num);
+    }
   }
 }
 
@@ -400,10 +485,10 @@ __device__ __forceinline__ void move_direct(const Chain &ch, int64_t idx, double
                                             Move &mv) {
   if (threadIdx.x == 0) {
     mv.idx = (int)idx;
-    mv.q = ch.pq[idx];
-    mv.r[0] = ch.px[idx];
-    mv.r[1] = ch.py[idx];
-    mv.r[2] = ch.pz[idx];
+    mv.q = glb(ch.pq)[idx];
+    mv.r[0] = glb(ch.px)[idx];
+    mv.r[1] = glb(ch.py)[idx];
+    mv.r[2] = glb(ch.pz)[idx];
     mv.rn[0] = wrap_coord(x, ch.a);
     mv.rn[1] = wrap_coord(y, ch.a);
     mv.rn[2] = wrap_coord(z, ch.a);
@@ -424,8 +509,8 @@ __global__ void __launch_bounds__(WG_SINGLE) k_propose_one(Chain ch, Tabs tb, in
   move_direct(ch, idx, x, y, z, mv);
   ProposeOut po = propose_wg<GS, PM, R>(ch, tb, mv, sm, [](int) {});
   if (threadIdx.x == 0) {
-    ch.scratch[0] = po.dE;
-    ch.scratch[1] = po.singular;
+    glb(ch.scratch)[0] = po.dE;
+    glb(ch.scratch)[1] = po.singular;
   }
 }
 
@@ -454,7 +539,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_accept_book(Chain ch, Tabs tb, in
   __syncthreads();
   int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, dE, sm);
   writeback_lds(ch, tb, sm);
-  if (threadIdx.x == 0 && ovf) ch.status[0] = -7;
+  if (threadIdx.x == 0 && ovf) glb(ch.status)[0] = -7;
 }
 
 }  // namespace fmmdev
