@@ -269,14 +269,66 @@ __device__ __forceinline__ double sqrt_r(double v) { return sqrt(v); }
 __device__ __forceinline__ float sqrt_r(float v) { return sqrtf(v); }
 
 // R is the arithmetic type of the evaluation (double, or float in the mixed
-// precision mode); the results are stored as doubles.
+// precision mode); the results are handed on as doubles. The core forms,
+// in lane m, the column T_n^m for n = m .. p and passes each term
+// c T_n^m (conjugated for KIND 1 and 2, divided by r^(2n+1) for KIND 2) to
+// sink(j, n, re, im) with n = m + j. The recurrence runs unconditionally to
+// the uniform bound p (rows beyond a lane's last row reuse a valid constant
+// slot and are computed but not passed on) and its constants come through a
+// restrict-qualified pointer, so their loads can be issued ahead of the
+// dependent arithmetic; results leave through the sink only.
+template <int GS, int PMAX, int KIND, typename R, typename Sink>
+__device__ __forceinline__ void harmonics_core(int lane, const Tabs &tb, const R *__restrict__ rec, R x, R y, R z,
+                                               R c, Sink &&sink) {
+  const int p = tb.p, Cs = tb.Cs;
+  const int m = lane;
+  const R r2 = x * x + y * y + z * z;
+  // (x + i y)^m and, for KIND 2, |x|^-(2m+1), by a multiplicative scan over the lanes
+  R wr = m == 0 ? R(1) : x, wi = m == 0 ? R(0) : y;
+  R inv_r2 = R(0), s = R(1);
+  if (KIND == 2) {
+    inv_r2 = R(1) / r2;
+    s = m == 0 ? sqrt_r(inv_r2) : inv_r2;
+  }
+  scan_step<GS, 1, R>(lane, wr, wi, s, KIND == 2);
+  if (m > p) return;
+  const R cm = rec[2 * Cs + m];
+  R tr = wr * cm, ti = wi * cm;
+  R pr = R(0), pi = R(0);  // T_{n-2}
+  const R im_sign = (KIND == 0) ? R(1) : R(-1);
+#pragma unroll
+  for (int j = 0; j <= PMAX; ++j) {
+    if (j <= p) {  // uniform over the group
+      if (j > 0) {
+        const int n = m + j <= p ? m + j : p;  // a valid slot for rows beyond p
+        const int sl = n * n + n + m;
+        R a = rec[sl] * z, b = rec[Cs + sl] * r2;
+        R nr = a * tr - b * pr;
+        R ni = a * ti - b * pi;
+        pr = tr;
+        pi = ti;
+        tr = nr;
+        ti = ni;
+        if (KIND == 2) s *= inv_r2;
+      }
+      if (m + j <= p) {
+        const R f = c * s;
+        sink(j, m + j, (double)(f * tr), (double)(im_sign * f * ti));
+      }
+    }
+  }
+}
+
+// One group of GS lanes evaluates the table for one point into the
+// real-layout buffer buf (C doubles): stored, or added with ACC. Each lane
+// runs only its own rows (n <= p), loading the constants as it goes; for a
+// single point this keeps the fewest registers live.
 template <int GS, int PMAX, int KIND, bool ACC, typename R = double>
 __device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const R *__restrict__ rec, R x, R y, R z,
                                                 R c, double *__restrict__ buf) {
   const int p = tb.p, Cs = tb.Cs;
   const int m = lane;
   const R r2 = x * x + y * y + z * z;
-  // (x + i y)^m and, for KIND 2, |x|^-(2m+1), by a multiplicative scan over the lanes
   R wr = m == 0 ? R(1) : x, wi = m == 0 ? R(0) : y;
   R inv_r2 = R(0), s = R(1);
   if (KIND == 2) {
@@ -316,6 +368,53 @@ __device__ __forceinline__ void group_harmonics(int lane, const Tabs &tb, const 
           buf[sn] += (double)(im_sign * f * ti);
         else
           buf[sn] = (double)(im_sign * f * ti);
+      }
+    }
+  }
+}
+
+// Column sums in registers: lane m holds sum c T_n^m for n = m + j in
+// re[j], im[j]. Several points are added without touching memory; flush()
+// then writes the column once. The additions are those of an accumulation
+// in memory, in the same order.
+template <int PMAX>
+struct ColSum {
+  double re[PMAX + 1], im[PMAX + 1];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int j = 0; j <= PMAX; ++j) re[j] = im[j] = 0.0;
+  }
+};
+
+template <int GS, int PMAX, int KIND, typename R = double>
+__device__ __forceinline__ void group_harmonics_sum(int lane, const Tabs &tb, const R *__restrict__ rec, R x, R y,
+                                                    R z, R c, ColSum<PMAX> &acc) {
+  harmonics_core<GS, PMAX, KIND, R>(lane, tb, rec, x, y, z, c, [&](int j, int, double re, double im) {
+    acc.re[j] += re;
+    acc.im[j] += im;
+  });
+}
+
+// write (or add, with ACC) a group's column sums into the real-layout buffer
+template <int PMAX, bool ACC>
+__device__ __forceinline__ void flush_cols(int lane, const Tabs &tb, const ColSum<PMAX> &acc, double *buf) {
+  const int p = tb.p, m = lane;
+  if (m > p) return;
+#pragma unroll
+  for (int j = 0; j <= PMAX; ++j) {
+    const int n = m + j;
+    if (n <= p) {
+      const int sp = n * n + n + m;
+      if (ACC)
+        buf[sp] += acc.re[j];
+      else
+        buf[sp] = acc.re[j];
+      if (m > 0) {
+        const int sn = n * n + n - m;
+        if (ACC)
+          buf[sn] += acc.im[j];
+        else
+          buf[sn] = acc.im[j];
       }
     }
   }

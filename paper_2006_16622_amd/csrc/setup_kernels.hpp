@@ -98,7 +98,7 @@ __global__ void k_bin_finalize(const Chain *chains) {
 // P2M on the leaves, Eq. (multipole_expansion_coefficients), scaled by the
 // leaf size: M^_n^m = sum q (|s|/h)^n Y_n^{-m}; one lane group per leaf
 template <int GS, int PM>
-__global__ void k_p2m_leaf(const Chain *chains, Tabs tb) {
+__global__ void __launch_bounds__(WG_SETUP) k_p2m_leaf(const Chain *chains, Tabs tb) {
   constexpr int NG = WG_SETUP / GS;
   extern __shared__ double lds[];
   const Chain &ch = chains[blockIdx.y];
@@ -113,11 +113,14 @@ __global__ void k_p2m_leaf(const Chain *chains, Tabs tb) {
   for (int s = lane; s < Cs; s += GS) buf[s] = 0.0;
   __builtin_amdgcn_wave_barrier();
   int cnt = ch.bin_cnt[c];
+  ColSum<PM> cs;
+  cs.zero();
   for (int j = 0; j < cnt; ++j) {
     double4 pj = ch.bin_p[(size_t)c * ch.B + j];
-    group_harmonics<GS, PM, 1, true>(lane, tb, tb.rec, (pj.x - (cx + 0.5) * h) / h,
-                                     (pj.y - (cy + 0.5) * h) / h, (pj.z - (cz + 0.5) * h) / h, pj.w, buf);
+    group_harmonics_sum<GS, PM, 1>(lane, tb, tb.rec, (pj.x - (cx + 0.5) * h) / h, (pj.y - (cy + 0.5) * h) / h,
+                                   (pj.z - (cz + 0.5) * h) / h, pj.w, cs);
   }
+  flush_cols<PM, false>(lane, tb, cs, buf);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   double *dst = ch.Mp + ch.mp_off[ch.L] + (size_t)c * Cs;
@@ -361,7 +364,7 @@ __global__ void k_lattice_init(const Chain *chains, Tabs tb) {
 // the particle itself, images included); block partial sums of
 // 1/2 q_i phi_i written to ch.red[block]
 template <int GS, int PM>
-__global__ void k_energy(const Chain *chains, Tabs tb) {
+__global__ void __launch_bounds__(WG_SETUP) k_energy(const Chain *chains, Tabs tb) {
   constexpr int NG = WG_SETUP / GS;
   extern __shared__ double lds[];
   __shared__ double red[WG_SETUP];
