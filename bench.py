@@ -14,6 +14,8 @@ Also measured in the same run and reported beside the headline value:
 * the batched form: 256 independent chains of uneven size and depth, set up
   in one pass and run in one launch, in FP64 and in mixed precision, as
   aggregate steps/s;
+* the scaling sweep N = 10^3 .. 10^6 of the propose and accept times of
+  the whole-GPU chain, fitted to the paper's performance model;
 * in the cpu_baseline leg: the FP64 oracle's per-step rate, the Ewald
   oracle's, and the dE error of both precisions against Ewald on proposals
   from the initial rock-salt state.
@@ -42,10 +44,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
 # they were taken on; otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "9f89b951c9c2c4403a4fdeae1b1740c472770e19924bbe4dc8f17f6b844ceed3",
+    "src_sha256": "5a612eb1dad2bf6e00a5ffcf23060a6f8e6830eb081e07fd121b0427daea1789",
     "steps": 200000, "warmup": 2000,
-    "fetch_kib": 35909062.625, "fetch_scale": 2.0,
-    "write_kib": 91733286.28125, "write_scale": 1.0,
+    "fetch_kib": 63126343.25, "fetch_scale": 2.0,
+    "write_kib": 91758462.6875, "write_scale": 1.0,
 }
 
 
@@ -239,6 +241,45 @@ def run_batched(seed=4, steps=10000, nchains=256, flags=0, resetup_every=0):
             "status": [s["status"] for s in st if s["status"] != 0][:4]}
 
 
+SWEEP_N = (1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000, 500000, 1000000)
+
+
+def run_sweep(steps=2000, warmup=300):
+    """Propose and accept time of the whole-GPU chain for N = 10^3 .. 10^6
+    uniform charges (about 3 per leaf cell, steps of 0.1 mean spacing), and
+    the least-squares fit of each stage to the paper's performance model
+    T(N) = tau + gamma L + kappa N / N_cell + sigma N (Sec. 5)."""
+    import workloads as W
+    from paper_2006_16622_amd import Chain, run_chains
+    import torch
+    rows = []
+    for i, n in enumerate(SWEEP_N):
+        depth = max(2, int(round(math.log(n / 3.0, 8))))
+        wl = W.uniform(n, depth, 12, 0.1 * n ** (-1.0 / 3.0), seed=50 + i, key=30 + i)
+        ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+        run_chains([ch], warmup, wl.seed, 1.0, wl.max_step, t0=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = run_chains([ch], steps, wl.seed, 1.0, wl.max_step, t0=warmup)[0]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        acc = max(1, st["accepted"])
+        rows.append({"n": n, "depth": depth, "L": depth + 1, "n_per_leaf": n / 8 ** depth,
+                     "t_prop_us": st["t_propose_us"] / steps,
+                     "t_acc_us": (st["t_accept_us"] + st["t_wait_us"]) / acc,
+                     "nu": st["accepted"] / steps, "steps_per_s": steps / dt})
+        ch.close()
+        log(f"[bench] sweep n={n} d={depth}: prop {rows[-1]['t_prop_us']:.2f} us, acc {rows[-1]['t_acc_us']:.2f} us")
+    A = np.array([[1.0, r["L"], r["n"] / 8 ** (r["L"] - 1), r["n"]] for r in rows])
+    fit = {}
+    for stage in ("prop", "acc"):
+        y = np.array([r[f"t_{stage}_us"] for r in rows])
+        coef = np.linalg.lstsq(A, y, rcond=None)[0]
+        fit[stage] = {"tau_us": coef[0], "gamma_us": coef[1], "kappa_us": coef[2], "sigma_us": coef[3]}
+    return {"model": "T(N) = tau + gamma L + kappa N/N_cell + sigma N (least squares, microseconds)",
+            "p": 12, "precision": "f64", "mode": "whole GPU", "steps": steps, "rows": rows, "fit": fit}
+
+
 def run_single_mixed(wl, steps, warmup, resetup_every=10000):
     from paper_2006_16622_amd import FMM_MC_MIXED, Chain, run_chains
     import torch
@@ -262,6 +303,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=10000)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the N = 1e3 .. 1e6 scaling sweep")
     ap.add_argument("--mode", type=int, default=0, help="0 auto, 1 one workgroup, 2 whole GPU")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -348,6 +390,9 @@ def main():
         log("[bench] batched 256 chains, mixed precision")
         out["batched_mixed"] = run_batched(steps=args.batched_steps, flags=1, resetup_every=10000)
         log(f"[bench] batched mixed {out['batched_mixed']['value']:.1f} steps/s")
+    if not args.no_sweep:
+        log("[bench] scaling sweep")
+        out["sweep"] = run_sweep()
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, out["config"]["acceptance"])
