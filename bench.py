@@ -248,7 +248,7 @@ def run_sweep(steps=2000, warmup=300):
     """Propose and accept time of the whole-GPU chain for N = 10^3 .. 10^6
     uniform charges (about 3 per leaf cell, steps of 0.1 mean spacing), and
     the least-squares fit of each stage to the paper's performance model
-    T(N) = tau + gamma L + kappa N / N_cell + sigma N (Sec. 5)."""
+    T(N) = tau + gamma L + kappa N / N_cell + sigma N (Sec. 5.4)."""
     import workloads as W
     from paper_2006_16622_amd import Chain, run_chains
     import torch
