@@ -83,6 +83,8 @@ def _load():
         "orc_setup_fmm": (None, [vp, ctypes.c_int]),
         "orc_setup_direct": (None, [vp]),
         "orc_setup_none": (None, [vp]),
+        "orc_setup_multipole": (None, [vp, ctypes.c_int]),
+        "orc_get_multipole": (None, [vp, ctypes.c_int, ctypes.c_int, _dp]),
         "orc_propose": (ctypes.c_double, [vp, ctypes.c_int, _dp]),
         "orc_accept": (None, [vp, ctypes.c_int, _dp]),
         "orc_energy": (ctypes.c_double, [vp]),
@@ -251,6 +253,11 @@ class Multilevel:
     use: for sampled checks at full size), ``"direct"`` (Alg. L.3) or
     ``"none"`` (zero expansions, lattice moments only: timing of the
     per-step cost, never a reference value).
+
+    ``setup="multipole"`` selects the multipole-based variant of Sec. 3.3
+    (Alg. M.1-M.3, multipoles formed directly per level);
+    ``"multipole_upward"`` is the same variant with the multipoles formed by
+    the FMM upward pass (P2M, M2M).
     """
 
     def __init__(self, pos, q, box: float, depth: int, p: int, setup: str = "fmm"):
@@ -271,6 +278,10 @@ class Multilevel:
             lib.orc_setup_direct(self._h)
         elif setup == "none":  # zero expansions: for timing the per-step cost only
             lib.orc_setup_none(self._h)
+        elif setup == "multipole":
+            lib.orc_setup_multipole(self._h, 0)
+        elif setup == "multipole_upward":
+            lib.orc_setup_multipole(self._h, 1)
         else:
             raise ValueError(setup)
 
@@ -297,6 +308,13 @@ class Multilevel:
     def local(self, level: int, cell: int) -> np.ndarray:
         out = np.zeros(self.C, dtype=np.complex128)
         _load().orc_get_local(self._h, int(level), int(cell), out.ctypes.data_as(_dp))
+        return out
+
+    def multipole(self, level: int, cell: int) -> np.ndarray:
+        """multipole coefficients of one cell (the live state of the
+        multipole-based variant; the setup state of the "fmm" setup)"""
+        out = np.zeros(self.C, dtype=np.complex128)
+        _load().orc_get_multipole(self._h, int(level), int(cell), out.ctypes.data_as(_dp))
         return out
 
     def K(self) -> np.ndarray:

@@ -524,6 +524,7 @@ typedef struct {
   cplx *S;         /* lattice sums, degree <= 2p */
   double dip[3];   /* dipole sum q_i r_i (wrapped positions) */
   int lazy;
+  int multipole;   /* the multipole-based variant of Sec. 3.3: Mp is the live state */
   move_rec *log;   /* lazy mode: accepted moves since setup */
   int nlog, caplog;
 } orc_t;
@@ -721,6 +722,7 @@ static cplx *local_of(orc_t *st, int l, int lin) {
  * M2L of each cell to its first use. */
 void orc_setup_fmm(orc_t *st, int lazy) {
   st->lazy = lazy;
+  st->multipole = 0;
   st->nlog = 0;
   upward_pass(st);
   init_lattice(st);
@@ -747,6 +749,7 @@ void orc_setup_fmm(orc_t *st, int lazy) {
  * core; it is never compared against. */
 void orc_setup_none(orc_t *st) {
   st->lazy = 0;
+  st->multipole = 0;
   st->nlog = 0;
   init_lattice(st);
   for (int l = 2; l <= st->L; ++l) {
@@ -761,6 +764,7 @@ void orc_setup_none(orc_t *st) {
  * interaction list of its cell (images included, Sec. 3.4). */
 void orc_setup_direct(orc_t *st) {
   st->lazy = 0;
+  st->multipole = 0;
   st->nlog = 0;
   init_lattice(st);
   for (int l = 2; l <= st->L; ++l) {
@@ -783,6 +787,59 @@ void orc_setup_direct(orc_t *st) {
       }
     }
   }
+}
+
+/* Initialisation of the multipole-based variant (Sec. 3.3). With
+ * upward == 0 it follows Alg. M.3: on every level 2..L, every charge is
+ * added to the multipole expansion of its own cell, Eq.
+ * (multipole_expansion_coefficients). With upward != 0 the same
+ * coefficients come from the FMM upward pass (P2M on the leaves, then M2M),
+ * which reproduces them up to rounding since M2M loses nothing at orders
+ * <= p. Levels 1 and the lattice moments K, E are those of Sec. 3.4. */
+void orc_setup_multipole(orc_t *st, int upward) {
+  st->lazy = 0;
+  st->nlog = 0;
+  st->multipole = 1;
+  if (upward) {
+    upward_pass(st);
+  } else {
+    for (int l = 2; l <= st->L; ++l) {
+      int n = nside(l);
+      size_t nc = (size_t)n * n * n;
+      free(st->Mp[l]);
+      st->Mp[l] = (cplx *)calloc(nc * st->C, sizeof(cplx));
+      for (int i = 0; i < st->N; ++i) {
+        int c[3];
+        double R[3];
+        locate(st, l, &st->pos[3 * i], c);
+        cell_centre(st, l, c, R);
+        orc_p2m(st->p, st->q[i], &st->pos[3 * i], R, (double *)&st->Mp[l][(size_t)cell_lin(n, c) * st->C]);
+      }
+    }
+  }
+  init_lattice(st);
+}
+
+/* the far field of the multipole-based variant at x: on every level
+ * l = 2..L, the multipole expansion of every cell (image) in the
+ * interaction list of the cell of x, evaluated at x (the inner loop of
+ * Alg. M.1, over the extended domain of Sec. 3.4) */
+static double m2p_far(orc_t *st, const double *x) {
+  double acc = 0.0;
+  for (int l = st->L; l >= 2; --l) {
+    int n = nside(l), a[3], oct[3], off[189 * 3];
+    double h = st->a / (double)n;
+    locate(st, l, x, a);
+    for (int k = 0; k < 3; ++k) oct[k] = a[k] & 1;
+    int cnt = orc_il_offsets(oct, off);
+    for (int j = 0; j < cnt; ++j) {
+      int b[3] = {a[0] + off[3 * j], a[1] + off[3 * j + 1], a[2] + off[3 * j + 2]};
+      int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
+      double R[3] = {(b[0] + 0.5) * h, (b[1] + 0.5) * h, (b[2] + 0.5) * h};
+      acc += orc_m2p(st->p, (double *)&st->Mp[l][(size_t)cell_lin(n, s) * st->C], x, R);
+    }
+  }
+  return acc;
 }
 
 /* sum of q_j / |x - r_j - a nu| over the particles of the 27 leaf cells
@@ -835,13 +892,19 @@ static double lattice_energy(const orc_t *st, const cplx *K, const cplx *E) {
  * where the new-side direct sum leaves out the moving charge's old images
  * lying in the near region together with the matching self terms (the two
  * cancel exactly), and the last term converts the cube-order lattice sum
- * to tin-foil boundary conditions. newpos is wrapped first. */
+ * to tin-foil boundary conditions. newpos is wrapped first. In the
+ * multipole-based variant (Sec. 3.3) the first sum is replaced by
+ * q [Phi_far(r') - Phi_far(r)], the multipole expansions of the interaction
+ * lists of both cells on every level (Alg. M.1). */
 double orc_propose(orc_t *st, int k, const double *newpos_in) {
   double a = st->a, q = st->q[k], rn[3], *r = &st->pos[3 * k];
   for (int i = 0; i < 3; ++i) rn[i] = orc_wrap(newpos_in[i], a);
   double dE = 0.0;
+  /* long range, multipole-based variant (Alg. M.1): the expansions of the
+   * interaction lists of both cells on every level */
+  if (st->multipole) dE += q * (m2p_far(st, rn) - m2p_far(st, r));
   /* long range: per-level local expansions, ancestors of both cells */
-  for (int l = st->L; l >= 2; --l) {
+  for (int l = st->L; l >= 2 && !st->multipole; --l) {
     int n = nside(l), c0[3], c1[3];
     double R0[3], R1[3];
     locate(st, l, r, c0);
@@ -891,14 +954,28 @@ double orc_propose(orc_t *st, int k, const double *newpos_in) {
 /* Accept, Alg. L.2 with the periodic modifications of Sec. 3.4: for every
  * level l = 2..L subtract the charge at r from the local expansion of every
  * cell (image) in IL(a_l) and add it at r' to every cell in IL(a'_l);
- * update K, E, the dipole, the position and the leaf lists. */
+ * update K, E, the dipole, the position and the leaf lists. The
+ * multipole-based variant updates instead the multipole expansions of the
+ * old and new cell on every level (Alg. M.2). */
 void orc_accept(orc_t *st, int k, const double *newpos_in) {
   double a = st->a, q = st->q[k], rn[3], r[3];
   for (int i = 0; i < 3; ++i) {
     rn[i] = orc_wrap(newpos_in[i], a);
     r[i] = st->pos[3 * k + i];
   }
-  for (int l = st->L; l >= 2; --l) {
+  /* multipole-based variant (Alg. M.2): the charge leaves the multipole
+   * expansion of its old cell and joins that of its new cell, per level */
+  for (int l = st->L; l >= 2 && st->multipole; --l) {
+    int n = nside(l), c0[3], c1[3];
+    double R0[3], R1[3];
+    locate(st, l, r, c0);
+    locate(st, l, rn, c1);
+    cell_centre(st, l, c0, R0);
+    cell_centre(st, l, c1, R1);
+    orc_p2m(st->p, -q, r, R0, (double *)&st->Mp[l][(size_t)cell_lin(n, c0) * st->C]);
+    orc_p2m(st->p, q, rn, R1, (double *)&st->Mp[l][(size_t)cell_lin(n, c1) * st->C]);
+  }
+  for (int l = st->L; l >= 2 && !st->multipole; --l) {
     int n = nside(l);
     double h = a / (double)n;
     for (int side = 0; side < 2; ++side) {
@@ -949,7 +1026,8 @@ double orc_energy(orc_t *st) {
   double U = 0.0;
   for (int i = 0; i < st->N; ++i) {
     double *r = &st->pos[3 * i], phi = 0.0;
-    for (int l = 2; l <= st->L; ++l) {
+    if (st->multipole) phi += m2p_far(st, r);
+    for (int l = 2; l <= st->L && !st->multipole; ++l) {
       int n = nside(l), c[3];
       double R[3];
       locate(st, l, r, c);
@@ -969,6 +1047,12 @@ double orc_energy(orc_t *st) {
 /* copy of L^Delta of one cell (complex, (p+1)^2) */
 void orc_get_local(orc_t *st, int l, int lin, double *out) {
   memcpy(out, local_of(st, l, lin), sizeof(cplx) * st->C);
+}
+
+/* copy of the multipole expansion of one cell (complex, (p+1)^2); valid
+ * after orc_setup_multipole, or after orc_setup_fmm for the setup state */
+void orc_get_multipole(orc_t *st, int l, int lin, double *out) {
+  memcpy(out, &st->Mp[l][(size_t)lin * st->C], sizeof(cplx) * st->C);
 }
 
 void orc_get_K(orc_t *st, double *out) { memcpy(out, st->K, sizeof(cplx) * st->C); }
