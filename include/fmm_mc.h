@@ -54,6 +54,17 @@ extern "C" {
 
 /* flags */
 #define FMM_MC_MIXED 0x1u /* FP32 L2P, near field and setup M2L; FP64 elsewhere */
+/* The multipole-based variant of Sec. 3.3 (Alg. M.1-M.3) in place of the
+ * local-expansion method: each level keeps the multipole expansion of every
+ * cell; a proposal evaluates the multipoles of the interaction lists of the
+ * old and new cell on every level at the charge (2 x 189 x (L-1) M2P), an
+ * accept updates one multipole per level and side. Near field, self-image,
+ * far-lattice and tin-foil terms are those of the local method. The setup
+ * forms the multipoles by P2M and M2M (the result of Alg. M.3 up to
+ * rounding) and no local expansions; fmm_mc_dump_locals then returns
+ * FMM_MC_ESTATE. FP64 only: combined with FMM_MC_MIXED it is rejected with
+ * FMM_MC_EINVAL. Chains of one fmm_mc_run must all use the same variant. */
+#define FMM_MC_MULTIPOLE 0x2u
 
 typedef struct fmm_mc_ctx *fmm_mc_t;
 
@@ -171,6 +182,13 @@ int fmm_mc_get_positions(fmm_mc_t h, double *pos);
  * sqrt((n-|m|)!/(n+|m|)!) P_n^|m| e^{i m phi}, no Condon-Shortley phase);
  * cells ordered x + n (y + n z). */
 int fmm_mc_dump_locals(fmm_mc_t h, int level, double *out);
+
+/* Multipole expansion coefficients of every cell on `level` (1..L), in the
+ * layout of fmm_mc_dump_locals: M_n^m = sum q rho^n Y_n^{-m} about the cell
+ * centre, Eq. (multipole_expansion_coefficients). For the multipole-based
+ * variant this is its live state; for the local method, the multipoles of
+ * the last setup. */
+int fmm_mc_dump_multipoles(fmm_mc_t h, int level, double *out);
 
 /* Rebuild every expansion from the current (device-resident) positions:
  * the whole setup pass of fmm_mc_setup, captured into a HIP graph on the

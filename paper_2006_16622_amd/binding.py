@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FMM_MC_LIB", os.path.join(HERE, "libfmm_mc.so"))
 
 FMM_MC_MIXED = 0x1
+FMM_MC_MULTIPOLE = 0x2
 _ERRORS = {0: "ok", -1: "EINVAL", -2: "ERANGE", -3: "ENONNEUTRAL", -4: "ESINGULAR", -5: "ENOMEM",
            -6: "EDEVICE", -7: "EOVERFLOW", -8: "ESTATE"}
 
@@ -73,6 +74,7 @@ SYMBOLS = {
     "fmm_mc_running_energy": (ctypes.c_int, [_vp, _dp]),
     "fmm_mc_get_positions": (ctypes.c_int, [_vp, _dp]),
     "fmm_mc_dump_locals": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "fmm_mc_dump_multipoles": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "fmm_mc_resetup": (ctypes.c_int, [_vp]),
     "fmm_mc_autotune": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                        ctypes.POINTER(Tuning)]),
@@ -197,6 +199,12 @@ class Chain:
         C = (self.p + 1) ** 2
         out = np.zeros((8 ** (level - 1), C))
         _check(load_library().fmm_mc_dump_locals(self._h, int(level), _d(out)), "fmm_mc_dump_locals")
+        return out
+
+    def multipoles(self, level: int) -> np.ndarray:
+        C = (self.p + 1) ** 2
+        out = np.zeros((8 ** (level - 1), C))
+        _check(load_library().fmm_mc_dump_multipoles(self._h, int(level), _d(out)), "fmm_mc_dump_multipoles")
         return out
 
     def autotune(self, steps: int = 1000, beta: float = 1.0, max_step: float = 0.0) -> dict:

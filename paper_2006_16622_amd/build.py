@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmm_mc.so")
 SOURCES = ["fmm_mc.hip"]
-DEPS = ["fmm_mc.hip", "device_common.hpp", "mc_step.hpp", "run_kernels.hpp", "setup_kernels.hpp",
+DEPS = ["fmm_mc.hip", "device_common.hpp", "mc_step.hpp", "mp_step.hpp", "run_kernels.hpp", "setup_kernels.hpp",
         "host_ops.hpp"]
 
 HIPCC_FLAGS = [

@@ -58,6 +58,7 @@ struct Chain {
   double *mbox;                 // cross-workgroup mailbox (single-chain run)
   unsigned *sync;               // [4] sequence / done counters
   double *red;                  // partial sums of reductions
+  double *part;                 // [512] per-workgroup partial sums of the whole-GPU run
   double *stage;                // raw host positions (3N) then charges (N)
 };
 

@@ -208,7 +208,7 @@ struct Layout {
 
 enum {
   O_PX, O_PY, O_PZ, O_PQ, O_LEAF, O_SLOT, O_BCNT, O_BID, O_BP, O_LD, O_MP, O_K, O_H,
-  O_DIP, O_U, O_STATUS, O_SCRATCH, O_MBOX, O_SYNC, O_RED, O_STAGE, O_STATS, O_CHAIN, O_TILES, O_END
+  O_DIP, O_U, O_STATUS, O_SCRATCH, O_MBOX, O_SYNC, O_RED, O_PART, O_STAGE, O_STATS, O_CHAIN, O_TILES, O_END
 };
 
 int bin_capacity(int64_t n, int levels) {
@@ -259,6 +259,7 @@ void make_layout(int64_t n, int levels, int p, Layout &ly) {
   sz[O_SYNC] = 4 * 512;
   const int NG = WG_SETUP / group_size(p);
   sz[O_RED] = 8 * ((n + NG - 1) / NG + 64);
+  sz[O_PART] = 8 * 512;
   sz[O_STAGE] = 8 * 4 * n;
   sz[O_STATS] = 8 * 64;
   sz[O_CHAIN] = sizeof(Chain);
@@ -326,6 +327,7 @@ struct SetupLaunch {
   const Tabs *tb = nullptr;
   bool restage = false;
   bool fp32_m2l = false;
+  bool multipole = false;  // the multipole-based variant: no M2L
   int m2l_rows = 0;  // 96 or 192 (0: 96)
   int energy_mode = 2;
   hipEvent_t e1 = nullptr, e2 = nullptr;
@@ -369,12 +371,16 @@ int enqueue_setup(const SetupLaunch &S) {
   for (int l = S.max_levels; l >= 1; --l)
     hipLaunchKernelGGL(k_m2m, dim3(1 << (3 * (l - 1)), nc), dim3(256), 0, st, S.chains, tb, l);
   if (S.e1) HIPCHK(hipEventRecord(S.e1, st));
-  launch_m2l(S);
+  if (!S.multipole) launch_m2l(S);
   if (S.e2) HIPCHK(hipEventRecord(S.e2, st));
   hipLaunchKernelGGL(k_lattice_init, dim3(1, nc), dim3(NT), 0, st, S.chains, tb);
   with_variant(variant_of(S.p), [&](auto gs, auto pm) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value>),
-                       dim3(grid_for(S.max_n, NG), nc), dim3(NT), shm, st, S.chains, tb);
+    if (S.multipole)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value, true>),
+                         dim3(grid_for(S.max_n, NG), nc), dim3(NT), shm, st, S.chains, tb);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value>),
+                         dim3(grid_for(S.max_n, NG), nc), dim3(NT), shm, st, S.chains, tb);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy_final<decltype(gs)::value>), dim3(1, nc), dim3(64), 0, st,
                        S.chains, tb, S.energy_mode);
   });
@@ -397,6 +403,7 @@ SetupLaunch single_launch(fmm_mc_ctx *h) {
   S.Cs = h->Cs;
   S.tb = &h->tables->tabs;
   S.fp32_m2l = (h->flags & FMM_MC_MIXED) != 0;
+  S.multipole = (h->flags & FMM_MC_MULTIPOLE) != 0;
   S.m2l_rows = h->m2l_rows;
   return S;
 }
@@ -415,9 +422,14 @@ int compute_energy(fmm_mc_ctx *h, double *U) {
   constexpr int NT = WG_SETUP;
   const int NG = NT / h->GS;
   const size_t shm = (size_t)NG * h->Cs * sizeof(double);
+  const bool mp = (h->flags & FMM_MC_MULTIPOLE) != 0;
   with_variant(variant_of(h->p), [&](auto gs, auto pm) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value>),
-                       dim3(grid_for(h->n, NG), 1), dim3(NT), shm, h->stream, h->d_chain, tb);
+    if (mp)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value, true>),
+                         dim3(grid_for(h->n, NG), 1), dim3(NT), shm, h->stream, h->d_chain, tb);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy<decltype(gs)::value, decltype(pm)::value>),
+                         dim3(grid_for(h->n, NG), 1), dim3(NT), shm, h->stream, h->d_chain, tb);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_energy_final<decltype(gs)::value>), dim3(1, 1), dim3(64), 0, h->stream,
                        h->d_chain, tb, 0);
   });
@@ -451,6 +463,9 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
     return FMM_MC_EINVAL;
   if (!(box > 0.0) || !std::isfinite(box)) return FMM_MC_EINVAL;
   if (((uintptr_t)dev_ws) % 256) return FMM_MC_EINVAL;
+  if ((flags & ~(FMM_MC_MIXED | FMM_MC_MULTIPOLE)) ||
+      ((flags & FMM_MC_MIXED) && (flags & FMM_MC_MULTIPOLE)))
+    return FMM_MC_EINVAL;
   double qs = 0.0, qa = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     if (!finite3(pos + 3 * i) || !std::isfinite(q[i])) return FMM_MC_EINVAL;
@@ -491,7 +506,7 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
   {
     std::lock_guard<std::mutex> lk(g_mu);
     for (const auto &e : g_tune)
-      if (e.device == h->device && e.p == p && e.levels == levels && e.mixed == (flags & FMM_MC_MIXED)) {
+      if (e.device == h->device && e.p == p && e.levels == levels && e.mixed == flags) {
         h->m2l_rows = e.m2l_rows;
         h->helpers = e.helpers;
       }
@@ -539,6 +554,7 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
   ch.mbox = (double *)(w + ly.off[O_MBOX]);
   ch.sync = (unsigned *)(w + ly.off[O_SYNC]);
   ch.red = (double *)(w + ly.off[O_RED]);
+  ch.part = (double *)(w + ly.off[O_PART]);
   ch.stage = (double *)(w + ly.off[O_STAGE]);
   h->d_chain = (Chain *)(w + ly.off[O_CHAIN]);
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
@@ -690,11 +706,18 @@ int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
   if (idx < 0 || idx >= h->n) return FMM_MC_ERANGE;
   const Tabs &tb = h->tables->tabs;
   const size_t shm = smem_bytes(h->GS, h->tables->tabs, WG_SINGLE);
-  with_run_variant(h->p, h->flags & FMM_MC_MIXED, [&](auto gs, auto pm, auto rt) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_propose_one<decltype(gs)::value, decltype(pm)::value,
-                                                     typename decltype(rt)::type>), dim3(1),
-                       dim3(WG_SINGLE), shm, h->stream, h->ch, tb, idx, new_pos[0], new_pos[1], new_pos[2]);
-  });
+  if (h->flags & FMM_MC_MULTIPOLE)
+    with_variant(variant_of(h->p), [&](auto gs, auto pm) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_propose_one<decltype(gs)::value, decltype(pm)::value, double, true>),
+                         dim3(1), dim3(WG_SINGLE), shm, h->stream, h->ch, tb, idx, new_pos[0], new_pos[1],
+                         new_pos[2]);
+    });
+  else
+    with_run_variant(h->p, h->flags & FMM_MC_MIXED, [&](auto gs, auto pm, auto rt) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_propose_one<decltype(gs)::value, decltype(pm)::value,
+                                                       typename decltype(rt)::type>), dim3(1),
+                         dim3(WG_SINGLE), shm, h->stream, h->ch, tb, idx, new_pos[0], new_pos[1], new_pos[2]);
+    });
   HIPCHK(hipGetLastError());
   double r[2];
   HIPCHK(hipMemcpyAsync(r, h->ch.scratch, sizeof(r), hipMemcpyDeviceToHost, h->stream));
@@ -720,14 +743,20 @@ int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *
   const size_t shm = smem_bytes(h->GS, h->tables->tabs, NT);
   const int NG = NT / h->GS;
   const int nb = accept_blocks(h->ch.L, NG);
-  with_run_variant(h->p, h->flags & FMM_MC_MIXED, [&](auto gs, auto pm, auto rt) {
-    constexpr int G_ = decltype(gs)::value, P_ = decltype(pm)::value;
-    using R_ = typename decltype(rt)::type;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_blocks<G_, P_, R_>), dim3(nb), dim3(NT), shm, h->stream, h->ch, tb,
-                       idx, new_pos[0], new_pos[1], new_pos[2]);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_book<G_, P_>), dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx,
-                       new_pos[0], new_pos[1], new_pos[2], dE);
-  });
+  if (h->flags & FMM_MC_MULTIPOLE)
+    with_variant(variant_of(h->p), [&](auto gs, auto pm) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_book<decltype(gs)::value, decltype(pm)::value, true>), dim3(1),
+                         dim3(NT), shm, h->stream, h->ch, tb, idx, new_pos[0], new_pos[1], new_pos[2], dE);
+    });
+  else
+    with_run_variant(h->p, h->flags & FMM_MC_MIXED, [&](auto gs, auto pm, auto rt) {
+      constexpr int G_ = decltype(gs)::value, P_ = decltype(pm)::value;
+      using R_ = typename decltype(rt)::type;
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_blocks<G_, P_, R_>), dim3(nb), dim3(NT), shm, h->stream, h->ch,
+                         tb, idx, new_pos[0], new_pos[1], new_pos[2]);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_accept_book<G_, P_>), dim3(1), dim3(NT), shm, h->stream, h->ch, tb, idx,
+                         new_pos[0], new_pos[1], new_pos[2], dE);
+    });
   HIPCHK(hipGetLastError());
   int status = 0;
   HIPCHK(hipMemcpyAsync(&status, h->ch.status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -748,10 +777,11 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   for (int c = 0; c < n_chains; ++c) {
     if (!chains[c] || !chains[c]->ready) return FMM_MC_ESTATE;
     if (chains[c]->p != h0->p || chains[c]->device != h0->device || chains[c]->stream != h0->stream ||
-        ((chains[c]->flags ^ h0->flags) & FMM_MC_MIXED))
+        chains[c]->flags != h0->flags)
       return FMM_MC_ESTATE;
   }
   const bool mixed = (h0->flags & FMM_MC_MIXED) != 0;
+  const bool mp = (h0->flags & FMM_MC_MULTIPOLE) != 0;
   hipStream_t st = h0->stream;
   const Tabs &tb = h0->tables->tabs;
   const int GS = h0->GS;
@@ -818,7 +848,26 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   rp.tr_leaf = tr_leaf;
   rp.stats = d_stats;
   int G = 1;
-  if (single) {
+  if (single && mp) {
+    // workgroup 0 proposes and accepts, the others (one per CU at most)
+    // share the far-field items of each proposal
+    const int NG = NT / GS;
+    int ncu = 0, per = 0;
+    RUNCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
+    G = (mp_items(h0->ch.L) + NG - 1) / NG + 1;
+    if (h0->helpers > 0) G = std::min(G, h0->helpers + 1);
+    G = std::max(1, std::min(G, std::min(ncu, 448)));
+    hipError_t oe = hipSuccess;
+    with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
+      oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, k_run_single_mp<decltype(gs)::value, decltype(pm)::value>, NT, shm);
+    });
+    RUNCHK(oe);
+    if (per < 1) {
+      release();
+      return FMM_MC_EDEVICE;
+    }
+  } else if (single) {
     // workgroup 0 proposes, the others (one per CU at most) hold the accept
     // blocks; the busiest helper's speculative rows must fit its LDS
     const int NG = NT / GS;
@@ -877,12 +926,23 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
       Chain chv = h0->ch;
       void *args[] = {&chv, (void *)&tb, &rp};
       hipError_t e = hipSuccess;
-      with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
-        e = hipLaunchCooperativeKernel(
-            (const void *)k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>,
-            dim3(G), dim3(NT), args, shm, st);
-      });
+      if (mp)
+        with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
+          e = hipLaunchCooperativeKernel((const void *)k_run_single_mp<decltype(gs)::value, decltype(pm)::value>,
+                                         dim3(G), dim3(NT), args, shm, st);
+        });
+      else
+        with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
+          e = hipLaunchCooperativeKernel(
+              (const void *)k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>,
+              dim3(G), dim3(NT), args, shm, st);
+        });
       RUNCHK(e);
+    } else if (mp) {
+      with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value, double, true>),
+                           dim3(na), dim3(NT), shm, st, d_chains, tb, rp);
+      });
     } else {
       with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value,
@@ -1018,25 +1078,35 @@ int fmm_mc_get_positions(fmm_mc_t h, double *pos) {
   return FMM_MC_OK;
 }
 
-int fmm_mc_dump_locals(fmm_mc_t h, int level, double *out) {
-  if (!h || !h->ready) return FMM_MC_ESTATE;
-  if (!out || level < 2 || level > h->ch.L) return FMM_MC_EINVAL;
+// a level of the scaled expansions ch.X + off, unscaled (by h^-(n+1) for
+// local expansions, h^n for multipoles) into the host layout
+static int dump_level(fmm_mc_t h, const double *base, int level, bool multipole, double *out) {
   const long long nc = 1LL << (3 * (level - 1));
   std::vector<double> b((size_t)nc * h->Cs);
-  HIPCHK(hipMemcpyAsync(b.data(), h->ch.Ld + h->ch.ld_off[level], sizeof(double) * b.size(),
-                        hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(b.data(), base, sizeof(double) * b.size(), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
-  // undo the cell-size scaling: L_n = L^_n / h^{n+1}
   const double hcell = h->box / double(1 << (level - 1));
   for (long long c = 0; c < nc; ++c)
     for (int n = 0; n <= h->p; ++n) {
-      double sc = std::pow(hcell, -(n + 1));
+      const double sc = multipole ? std::pow(hcell, n) : std::pow(hcell, -(n + 1));
       for (int m = -n; m <= n; ++m) {
         int s = n * n + n + m;
         out[(size_t)c * h->C + s] = b[(size_t)c * h->Cs + s] * sc;
       }
     }
   return FMM_MC_OK;
+}
+
+int fmm_mc_dump_multipoles(fmm_mc_t h, int level, double *out) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (!out || level < 1 || level > h->ch.L) return FMM_MC_EINVAL;
+  return dump_level(h, h->ch.Mp + h->ch.mp_off[level], level, true, out);
+}
+
+int fmm_mc_dump_locals(fmm_mc_t h, int level, double *out) {
+  if (!h || !h->ready || (h->flags & FMM_MC_MULTIPOLE)) return FMM_MC_ESTATE;
+  if (!out || level < 2 || level > h->ch.L) return FMM_MC_EINVAL;
+  return dump_level(h, h->ch.Ld + h->ch.ld_off[level], level, false, out);
 }
 
 int fmm_mc_last_timing(fmm_mc_t h, double *out, int nout) {
@@ -1074,6 +1144,7 @@ static Chain rebase_chain(const Chain &c, const char *from, char *to) {
   r.mbox = rebase(c.mbox, from, to);
   r.sync = rebase(c.sync, from, to);
   r.red = rebase(c.red, from, to);
+  r.part = rebase(c.part, from, to);
   r.stage = rebase(c.stage, from, to);
   return r;
 }
@@ -1104,9 +1175,10 @@ int fmm_mc_autotune(fmm_mc_t h, int64_t steps, double beta, double max_step, fmm
   int rc = clone() ? 0 : FMM_MC_EDEVICE;
   // (a) M2L output rows per workgroup, timed on the clone (3 launches each)
   const int rows[2] = {96, 192};
+  const bool mp = (h->flags & FMM_MC_MULTIPOLE) != 0;
   double best = 1e300;
-  t.m2l_rows = 192;
-  for (int k = 0; k < 2 && !rc; ++k) {
+  t.m2l_rows = mp ? 96 : 192;  // the multipole-based variant has no M2L
+  for (int k = 0; k < 2 && !rc && !mp; ++k) {
     SetupLaunch S = single_launch(&sh);
     S.m2l_rows = rows[k];
     launch_m2l(S);
@@ -1126,7 +1198,10 @@ int fmm_mc_autotune(fmm_mc_t h, int64_t steps, double beta, double max_step, fmm
   // candidate from the same cloned state, in two interleaved passes (the
   // faster of the two counts); a smaller count than all blocks is taken
   // only if it is more than 2 % faster
-  const int nblk = accept_blocks(h->ch.L, WG_SINGLE / h->GS);
+  // units of helper work: accept blocks, or groups of far-field items in
+  // the multipole-based variant
+  const int NGs = WG_SINGLE / h->GS;
+  const int nblk = mp ? (mp_items(h->ch.L) + NGs - 1) / NGs : accept_blocks(h->ch.L, NGs);
   const int div[8] = {1, 2, 3, 4, 6, 8, 12, 16};
   for (int k = 0; k < 8; ++k) {
     const int cand = (nblk + div[k] - 1) / div[k];
@@ -1163,7 +1238,7 @@ int fmm_mc_autotune(fmm_mc_t h, int64_t steps, double beta, double max_step, fmm
   h->helpers = t.helpers;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    const uint32_t mixed = h->flags & FMM_MC_MIXED;
+    const uint32_t mixed = h->flags;
     bool found = false;
     for (auto &e : g_tune)
       if (e.device == h->device && e.p == h->p && e.levels == h->levels && e.mixed == mixed) {

@@ -111,12 +111,14 @@ struct ProposeOut {
 // the near region together with the matching self term (they cancel). The
 // bin records the bookkeeping of an accept needs are kept in LDS. `early`
 // is run by the last wavefront at the start, `spare` by the last wavefront
-// while the others evaluate the expansions.
+// while the others evaluate the expansions. With LOCAL false the first sum
+// (the local expansions) is left out: the multipole-based variant adds its
+// own far field.
 struct NoWork {
   __device__ void operator()(int) const {}
 };
 
-template <int GS, int PM, typename R, int NT, typename Spare, typename Early = NoWork>
+template <int GS, int PM, typename R, bool LOCAL = true, int NT, typename Spare, typename Early = NoWork>
 __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm,
                                  Spare &&spare, Early &&early = NoWork{}) {
   constexpr int NG = NT / GS;
@@ -126,7 +128,7 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
   int *ints = sm.ints;
   const double a = ch.a, q = mv.q;
   const int L = ch.L, d = ch.d, B = ch.B;
-  const int npts = 2 * d + 2;
+  const int npts = LOCAL ? 2 * d + 2 : 2;
   const int nL = 1 << (L - 1);
 
   if (t >= NT - 64) early(t - (NT - 64));
@@ -276,7 +278,7 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
 
   ProposeOut out;
   double dE = 0.0;
-  for (int l = 2; l <= L; ++l) {
+  for (int l = 2; l <= L && LOCAL; ++l) {
     int po = 2 + 2 * (l - 2);
     dE += q * (sm.vals[po + 1] - sm.vals[po]);
   }

@@ -20,7 +20,7 @@
 // step t is being proposed.
 #pragma once
 
-#include "mc_step.hpp"
+#include "mp_step.hpp"
 
 namespace fmmdev {
 
@@ -92,7 +92,7 @@ __device__ __forceinline__ void move_from_draw(const RunParams &rp, const Chain 
   }
 }
 
-template <int GS, int PM, typename R>
+template <int GS, int PM, typename R, bool MP = false>
 __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
   constexpr int NT = WG_BATCH;
   constexpr int NG = NT / GS;
@@ -130,9 +130,14 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
     locate_move_par(ch, mv);
     __syncthreads();
     const double u = s_u;
-    ProposeOut po = propose_wg<GS, PM, R>(ch, tb, mv, sm, [&](int lane) {
+    auto fetch = [&](int lane) {
       if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
-    });
+    };
+    ProposeOut po;
+    if constexpr (MP)
+      po = propose_mp_wg<GS, PM>(ch, tb, mv, sm, fetch);
+    else
+      po = propose_wg<GS, PM, R>(ch, tb, mv, sm, fetch);
     uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
     tick_prop += t_1 - t_0;
     if (t == 0) {
@@ -156,7 +161,10 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
     prev_idx = mv.idx;
     for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
     if (prev_acc) {
-      accept_all_wg<GS, PM, R>(ch, tb, mv, sm);
+      if constexpr (MP)
+        accept_mp_wg<GS, PM, NT>(ch, tb, mv, sm.rec);
+      else
+        accept_all_wg<GS, PM, R>(ch, tb, mv, sm);
       int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, po.dE, sm);
       if (t == 0) {
         nacc += 1;
@@ -203,6 +211,17 @@ __device__ __forceinline__ bool spin_until_ne(unsigned *p, unsigned old, unsigne
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   while (true) {
     val = ld_relaxed(p);
+    if (val != old) return true;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+// the same wait by a whole wavefront: the value is made uniform, so every
+// lane takes the same exit
+__device__ __forceinline__ bool wave_spin_until_ne(unsigned *p, unsigned old, unsigned &val, uint64_t limit) {
+  uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  while (true) {
+    val = __builtin_amdgcn_readfirstlane(ld_relaxed(p));
     if (val != old) return true;
     if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
     __builtin_amdgcn_s_sleep(1);
@@ -480,6 +499,233 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   }
 }
 
+// The whole-GPU chain of the multipole-based variant (Sec. 3.3). Its
+// expensive loops are in the proposal (Alg. M.1), so the helpers share the
+// proposal instead of the accept: workgroup 0 draws the move, posts it at
+// the start of its proposal and forms the near-field, self-image, lattice
+// and tin-foil terms; helper w evaluates the far-field items of its groups
+// (items (w-1) NG + g, stepping by (G-1) NG), adds them by a fixed tree and
+// posts the sum in part[w] with its done flag. Workgroup 0 adds the partial
+// sums in helper order, decides, and on accept updates the 2(L-1)
+// multipoles and the bookkeeping itself (Alg. M.2), releasing every store
+// before it posts the next move, so a helper always reads the multipoles
+// of the current state. Protocol words: sync[0] number of the latest move,
+// sync[2] stop, sync[3] error, sync[64 + w] done flag of helper w; the move
+// is in mailbox slot number & 1, which is rewritten only after every helper
+// has finished the move after it. Every wait is bounded.
+template <int GS, int PM>
+__global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs tb, RunParams rp) {
+  constexpr int NT = WG_SINGLE;
+  constexpr int NG = NT / GS;
+  extern __shared__ double lds[];
+  __shared__ Move mv;
+  __shared__ NextDraw nd;
+  __shared__ int s_flag, s_acc;
+  __shared__ unsigned s_seq;
+  __shared__ double s_u, s_far;
+  __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
+  const int t = threadIdx.x, w = blockIdx.x, G = gridDim.x;
+  if (t == 0) chl = ch_arg;
+  __syncthreads();
+  const Chain &ch = chl;
+  unsigned *mvseq = ch.sync, *stop = ch.sync + 2, *err = ch.sync + 3;
+  unsigned *doneflag = ch.sync + 64;
+  double *mb = ch.mbox;
+  Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
+  stage_lds(ch, tb, sm, w == 0);
+  __syncthreads();
+  if (w == 0) {
+    const int c = rp.chain_id ? rp.chain_id[0] : 0;
+    const double D = rp.max_step[c];
+    double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
+    int status = 0;
+    unsigned num = 0;  // move number of this launch
+    uint64_t tick_prop = 0, tick_acc = 0, tick_wait = 0;
+    bool prev_acc = false;
+    int prev_idx = -1;
+    double prev_rn[3] = {0, 0, 0};
+    const int64_t s0 = rp.first ? rp.first[0] : 0;
+    int64_t acc_launch = 0;
+    if (t == 0 && s0 < rp.steps) draw_into(rp, c, s0, ch, D, nd);
+    __syncthreads();
+    for (int64_t step = s0; step < rp.steps; ++step) {
+      uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
+      ++num;
+      if (t == 0) {
+        move_from_draw(rp, ch, nd, prev_acc, prev_idx, prev_rn, mv);
+        s_u = nd.u;
+      }
+      __syncthreads();
+      locate_move_par(ch, mv);
+      __syncthreads();
+      const double u = s_u;
+      ProposeOut po = propose_wg<GS, PM, double, false>(
+          ch, tb, mv, sm,
+          [&](int lane) {
+            if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
+          },
+          [&](int lane) {
+            if (lane == 0 && G > 1) {
+              const auto slot = glb(mb) + 8 * (num & 1);
+              slot[0] = (double)mv.idx;
+              slot[1] = mv.q;
+              for (int k = 0; k < 3; ++k) {
+                slot[2 + k] = mv.r[k];
+                slot[5 + k] = mv.rn[k];
+              }
+              st_release(mvseq, num);
+            }
+          });
+      uint64_t t_w = __builtin_amdgcn_s_memrealtime();
+      if (G > 1) {
+        // the helpers' partial sums, added in helper order
+        if (t < 64) {
+          const bool ok = spin_all_equal(doneflag, G, num, SPIN_LIMIT);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          double v = 0.0;
+          if (ok)
+            for (int hw = 1 + t; hw < G; hw += 64) v += glb(ch.part)[hw];
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+          if (t == 0) {
+            s_far = v;
+            s_flag = ok ? 0 : 1;
+          }
+        }
+        __syncthreads();
+      } else {
+        // no helpers: the workgroup evaluates every item itself
+        double f = m2p_far_part<GS, PM>(ch, tb, sm.rec, sm.il_off, mv, 0, NG);
+        f = wg_sum<NT>(f, sm.red);
+        if (t == 0) {
+          s_far = f;
+          s_flag = 0;
+        }
+        __syncthreads();
+      }
+      if (s_flag) {
+        status = -8;
+        break;
+      }
+      const double dE = po.dE + mv.q * s_far;
+      uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
+      tick_prop += t_w - t_0;
+      tick_wait += t_1 - t_w;
+      if (t == 0) {
+        int acc = !po.singular && (u < exp(-rp.beta * dE));
+        s_acc = acc;
+        nprop += 1;
+        nsing += po.singular;
+        const int64_t o = (int64_t)c * rp.steps + step;
+        if (rp.tr_idx) glb(rp.tr_idx)[o] = mv.idx;
+        if (rp.tr_pos)
+          for (int k = 0; k < 3; ++k) glb(rp.tr_pos)[3 * o + k] = mv.rn[k];
+        if (rp.tr_dE) glb(rp.tr_dE)[o] = dE;
+        if (rp.tr_acc) glb(rp.tr_acc)[o] = (uint8_t)acc;
+        if (rp.tr_leaf) {
+          int n = 1 << (ch.L - 1);
+          glb(rp.tr_leaf)[o] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
+        }
+      }
+      __syncthreads();
+      prev_acc = s_acc;
+      prev_idx = mv.idx;
+      for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
+      if (prev_acc) {
+        accept_mp_wg<GS, PM, NT>(ch, tb, mv, sm.rec);
+        // each thread releases its own multipole stores; the next move is
+        // posted after the barriers of the bookkeeping
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, dE, sm);
+        if (t == 0) {
+          nacc += 1;
+          dEsum += dE;
+        }
+        tick_acc += __builtin_amdgcn_s_memrealtime() - t_1;
+        if (ovf) {
+          status = -7;
+          break;
+        }
+        if (rp.acc_limit && ++acc_launch >= rp.acc_limit) break;
+      }
+      // every step ends at a barrier (see the helper loop)
+      __syncthreads();
+    }
+    if (G > 1 && t == 0) {
+      st_release(stop, 1u);
+      st_release(mvseq, num + 1);
+    }
+    __syncthreads();
+    writeback_lds(ch, tb, sm);
+    if (t == 0) {
+      glb(rp.stats)[0] = nprop;
+      glb(rp.stats)[1] = nacc;
+      glb(rp.stats)[2] = nsing;
+      glb(rp.stats)[3] = dEsum;
+      glb(rp.stats)[4] = status;
+      glb(rp.stats)[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
+      glb(rp.stats)[6] = tick_acc * 0.01;
+      glb(rp.stats)[7] = tick_wait * 0.01;
+    }
+    return;
+  }
+  // ---- helper workgroups. The whole of wavefront 0 waits (a condition
+  // uniform over each wavefront) and every iteration ends at a barrier, so
+  // no per-thread branch at the end of one iteration can be merged by the
+  // compiler with the wait of the next.
+  unsigned cur = 0;
+  while (true) {
+    if (t < 64) {
+      unsigned v;
+      const bool ok = wave_spin_until_ne(mvseq, cur, v, SPIN_LIMIT);
+      int fl = ok ? 0 : 1;
+      if (ok) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the stop flag is stored before the number
+        const unsigned sv = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(glb(stop), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+        if (sv) fl = 2;
+      }
+      if (t == 0) {
+        s_seq = v;
+        s_flag = fl;
+      }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int f = s_flag;
+    const unsigned num = s_seq;
+    __syncthreads();
+    if (f == 1) {
+      if (t == 0) st_relaxed(err, 1u);
+      return;
+    }
+    if (f == 2) return;
+    cur = num;
+    if (t == 0) {
+      const auto slot = glb(mb) + 8 * (num & 1);
+      double m[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) m[k] = slot[k];
+      mv.idx = (int)m[0];
+      mv.q = m[1];
+      for (int k = 0; k < 3; ++k) {
+        mv.r[k] = m[2 + k];
+        mv.rn[k] = m[5 + k];
+      }
+    }
+    __syncthreads();
+    locate_move_par(ch, mv);
+    __syncthreads();
+    double fsum = m2p_far_part<GS, PM>(ch, tb, sm.rec, sm.il_off, mv, (w - 1) * NG, (G - 1) * NG);
+    fsum = wg_sum<NT>(fsum, sm.red);
+    if (t == 0) {
+      glb(ch.part)[w] = fsum;
+      st_release(&doneflag[w], num);
+    }
+    __syncthreads();
+  }
+}
+
 // single-call entry points (one proposal / one accept)
 __device__ __forceinline__ void move_direct(const Chain &ch, int64_t idx, double x, double y, double z,
                                             Move &mv) {
@@ -498,7 +744,7 @@ __device__ __forceinline__ void move_direct(const Chain &ch, int64_t idx, double
   __syncthreads();
 }
 
-template <int GS, int PM, typename R>
+template <int GS, int PM, typename R, bool MP = false>
 __global__ void __launch_bounds__(WG_SINGLE) k_propose_one(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                     double z) {
   constexpr int NT = WG_SINGLE;
@@ -507,7 +753,11 @@ __global__ void __launch_bounds__(WG_SINGLE) k_propose_one(Chain ch, Tabs tb, in
   Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
   move_direct(ch, idx, x, y, z, mv);
-  ProposeOut po = propose_wg<GS, PM, R>(ch, tb, mv, sm, [](int) {});
+  ProposeOut po;
+  if constexpr (MP)
+    po = propose_mp_wg<GS, PM>(ch, tb, mv, sm, [](int) {});
+  else
+    po = propose_wg<GS, PM, R>(ch, tb, mv, sm, [](int) {});
   if (threadIdx.x == 0) {
     glb(ch.scratch)[0] = po.dE;
     glb(ch.scratch)[1] = po.singular;
@@ -526,7 +776,9 @@ __global__ void __launch_bounds__(WG_SINGLE) k_accept_blocks(Chain ch, Tabs tb, 
   accept_block<GS, PM, R>(ch, tb, mv, blockIdx.x, sm);
 }
 
-template <int GS, int PM>
+// the bookkeeping of one accepted move; in the multipole-based variant
+// (MP) also its multipole updates (Alg. M.2)
+template <int GS, int PM, bool MP = false>
 __global__ void __launch_bounds__(WG_SINGLE) k_accept_book(Chain ch, Tabs tb, int64_t idx, double x, double y,
                                                     double z, double dE) {
   constexpr int NT = WG_SINGLE;
@@ -535,6 +787,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_accept_book(Chain ch, Tabs tb, in
   Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
   move_direct(ch, idx, x, y, z, mv);
+  if constexpr (MP) accept_mp_wg<GS, PM, NT>(ch, tb, mv, sm.rec);
   load_bin_records(ch, mv, sm);
   __syncthreads();
   int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, dE, sm);

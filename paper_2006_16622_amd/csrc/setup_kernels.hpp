@@ -5,7 +5,7 @@
 #pragma once
 
 #include "device_common.hpp"
-#include "mc_step.hpp"
+#include "mp_step.hpp"
 
 namespace fmmdev {
 
@@ -362,8 +362,10 @@ __global__ void k_lattice_init(const Chain *chains, Tabs tb) {
 
 // per-particle potential phi_i = sum_l Psi^D_l(r_i) + near(r_i) (excluding
 // the particle itself, images included); block partial sums of
-// 1/2 q_i phi_i written to ch.red[block]
-template <int GS, int PM>
+// 1/2 q_i phi_i written to ch.red[block]. In the multipole-based variant
+// (MP) the far part is the sum over levels of the multipoles of the
+// interaction list of the particle's cell, evaluated at r_i (Sec. 3.3).
+template <int GS, int PM, bool MP = false>
 __global__ void __launch_bounds__(WG_SETUP) k_energy(const Chain *chains, Tabs tb) {
   constexpr int NG = WG_SETUP / GS;
   extern __shared__ double lds[];
@@ -378,7 +380,17 @@ __global__ void __launch_bounds__(WG_SETUP) k_energy(const Chain *chains, Tabs t
     const double a = ch.a;
     double r[3] = {ch.px[i], ch.py[i], ch.pz[i]};
     double phi = 0.0;
-    for (int l = 2; l <= ch.L; ++l) {
+    if constexpr (MP) {
+      double far = 0.0;
+      for (int l = 2; l <= ch.L; ++l) {
+        const int n = 1 << (l - 1);
+        int c[3];
+        for (int k = 0; k < 3; ++k) c[k] = cell_coord(r[k], ch.inv_h[l], n);
+        for (int k = 0; k < 189; ++k) far += m2p_cell<GS, PM>(ch, tb, tb.rec, tb.il_off, l, c, r, k, lane);
+      }
+      phi += group_sum<GS>(far);
+    }
+    for (int l = 2; l <= ch.L && !MP; ++l) {
       int n = 1 << (l - 1);
       double h = a / n;
       int c[3];
