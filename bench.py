@@ -14,8 +14,10 @@ Also measured in the same run and reported beside the headline value:
 * the batched form: 256 independent chains of uneven size and depth, set up
   in one pass and run in one launch, in FP64 and in mixed precision, as
   aggregate steps/s;
+* the multipole-based variant (Alg. M.1-M.3) on the same chain;
 * the scaling sweep N = 10^3 .. 10^6 of the propose and accept times of
-  the whole-GPU chain, fitted to the paper's performance model;
+  the whole-GPU chain, local method and multipole variant, each fitted to
+  the paper's performance model, with the speedup of the local method;
 * in the cpu_baseline leg: the FP64 oracle's per-step rate, the Ewald
   oracle's, and the dE error of both precisions against Ewald on proposals
   from the initial rock-salt state.
@@ -244,40 +246,96 @@ def run_batched(seed=4, steps=10000, nchains=256, flags=0, resetup_every=0):
 SWEEP_N = (1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000, 500000, 1000000)
 
 
-def run_sweep(steps=2000, warmup=300):
-    """Propose and accept time of the whole-GPU chain for N = 10^3 .. 10^6
-    uniform charges (about 3 per leaf cell, steps of 0.1 mean spacing), and
-    the least-squares fit of each stage to the paper's performance model
-    T(N) = tau + gamma L + kappa N / N_cell + sigma N (Sec. 5.4)."""
-    import workloads as W
-    from paper_2006_16622_amd import Chain, run_chains
-    import torch
-    rows = []
-    for i, n in enumerate(SWEEP_N):
-        depth = max(2, int(round(math.log(n / 3.0, 8))))
-        wl = W.uniform(n, depth, 12, 0.1 * n ** (-1.0 / 3.0), seed=50 + i, key=30 + i)
-        ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p)
-        run_chains([ch], warmup, wl.seed, 1.0, wl.max_step, t0=0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = run_chains([ch], steps, wl.seed, 1.0, wl.max_step, t0=warmup)[0]
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        acc = max(1, st["accepted"])
-        rows.append({"n": n, "depth": depth, "L": depth + 1, "n_per_leaf": n / 8 ** depth,
-                     "t_prop_us": st["t_propose_us"] / steps,
-                     "t_acc_us": (st["t_accept_us"] + st["t_wait_us"]) / acc,
-                     "nu": st["accepted"] / steps, "steps_per_s": steps / dt})
-        ch.close()
-        log(f"[bench] sweep n={n} d={depth}: prop {rows[-1]['t_prop_us']:.2f} us, acc {rows[-1]['t_acc_us']:.2f} us")
+def _stage_times(st, steps, flags):
+    """per-proposal and per-accept times (us) from the kernel's own clock.
+    In the local method the helpers' wait belongs to the accept; in the
+    multipole-based variant it is the far field of the proposal."""
+    acc = max(1, st["accepted"])
+    if flags & 2:
+        return (st["t_propose_us"] + st["t_wait_us"]) / steps, st["t_accept_us"] / acc
+    return st["t_propose_us"] / steps, (st["t_accept_us"] + st["t_wait_us"]) / acc
+
+
+def _fit(rows):
     A = np.array([[1.0, r["L"], r["n"] / 8 ** (r["L"] - 1), r["n"]] for r in rows])
     fit = {}
     for stage in ("prop", "acc"):
         y = np.array([r[f"t_{stage}_us"] for r in rows])
         coef = np.linalg.lstsq(A, y, rcond=None)[0]
         fit[stage] = {"tau_us": coef[0], "gamma_us": coef[1], "kappa_us": coef[2], "sigma_us": coef[3]}
+    return fit
+
+
+def _model_t(f, n, L):
+    return f["tau_us"] + f["gamma_us"] * L + f["kappa_us"] * n / 8 ** (L - 1) + f["sigma_us"] * n
+
+
+def run_sweep(steps=2000, warmup=300, nu_paper=0.438):
+    """Propose and accept time of the whole-GPU chain of the local method and
+    of the multipole-based variant for N = 10^3 .. 10^6 uniform charges
+    (about 3 per leaf cell, steps of 0.1 mean spacing); the least-squares
+    fit of each stage to the paper's performance model
+    T(N) = tau + gamma L + kappa N / N_cell + sigma N, and the speedup of
+    the local method over the multipole variant, measured per step and
+    predicted from the fits at the paper's acceptance rate, with its limit
+    S_inf = (g_prop^mp + nu g_acc^mp) / (g_prop^loc + nu g_acc^loc)
+    (Sec. 5.4)."""
+    import workloads as W
+    from paper_2006_16622_amd import Chain, run_chains
+    import torch
+    rows = {0: [], 2: []}
+    for i, n in enumerate(SWEEP_N):
+        depth = max(2, int(round(math.log(n / 3.0, 8))))
+        wl = W.uniform(n, depth, 12, 0.1 * n ** (-1.0 / 3.0), seed=50 + i, key=30 + i)
+        for flags in (0, 2):
+            ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
+            run_chains([ch], warmup, wl.seed, 1.0, wl.max_step, t0=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = run_chains([ch], steps, wl.seed, 1.0, wl.max_step, t0=warmup)[0]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            tp, ta = _stage_times(st, steps, flags)
+            rows[flags].append({"n": n, "depth": depth, "L": depth + 1, "n_per_leaf": n / 8 ** depth,
+                                "t_prop_us": tp, "t_acc_us": ta, "nu": st["accepted"] / steps,
+                                "steps_per_s": steps / dt, "status": st["status"]})
+            ch.close()
+            log(f"[bench] sweep {'multipole' if flags else 'local'} n={n} d={depth}: prop {tp:.2f} us, "
+                f"acc {ta:.2f} us, {steps / dt:.0f} steps/s")
+    fit_loc, fit_mp = _fit(rows[0]), _fit(rows[2])
+    speed = []
+    for rl, rm in zip(rows[0], rows[2]):
+        n, L = rl["n"], rl["L"]
+        num = _model_t(fit_mp["prop"], n, L) + nu_paper * _model_t(fit_mp["acc"], n, L)
+        den = _model_t(fit_loc["prop"], n, L) + nu_paper * _model_t(fit_loc["acc"], n, L)
+        speed.append({"n": n, "measured": rl["steps_per_s"] / rm["steps_per_s"], "model": num / den})
+    g = lambda f, st: f[st]["gamma_us"]  # noqa: E731
+    s_inf = (g(fit_mp, "prop") + nu_paper * g(fit_mp, "acc")) / (g(fit_loc, "prop") + nu_paper * g(fit_loc, "acc"))
     return {"model": "T(N) = tau + gamma L + kappa N/N_cell + sigma N (least squares, microseconds)",
-            "p": 12, "precision": "f64", "mode": "whole GPU", "steps": steps, "rows": rows, "fit": fit}
+            "p": 12, "precision": "f64", "mode": "whole GPU", "steps": steps,
+            "rows": rows[0], "fit": fit_loc, "multipole": {"rows": rows[2], "fit": fit_mp},
+            "speedup_local_over_multipole": {"nu": nu_paper, "per_n": speed, "s_inf": s_inf}}
+
+
+def run_single_variant(wl, steps, warmup, flags, resetup_every=0, tune=False):
+    """one chain of the workload with the given flags, on the whole GPU"""
+    from paper_2006_16622_amd import Chain, run_chains
+    import torch
+    ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
+    t = ch.autotune(steps=2000, beta=wl.beta, max_step=wl.max_step) if tune else None
+    run_chains([ch], warmup, wl.seed, wl.beta, wl.max_step, t0=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = run_chains([ch], steps, wl.seed, wl.beta, wl.max_step, t0=warmup, resetup_every=resetup_every)[0]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ch.close()
+    tp, ta = _stage_times(st, steps, flags)
+    out = {"value": steps / dt, "unit": "MH steps/s", "steps": steps, "accepted": st["accepted"],
+           "status": st["status"], "t_prop_us": tp, "t_acc_us": ta}
+    if t is not None:
+        out["helpers"] = t["helpers"]
+    return out
 
 
 def run_single_mixed(wl, steps, warmup, resetup_every=10000):
@@ -383,6 +441,10 @@ def main():
     log("[bench] single chain, mixed precision")
     out["single_mixed"] = run_single_mixed(wl, args.steps, args.warmup)
     log(f"[bench] single chain mixed {out['single_mixed']['value']:.1f} steps/s")
+    log("[bench] single chain, multipole-based variant")
+    out["single_multipole"] = run_single_variant(wl, args.steps // 4, args.warmup, flags=2, tune=True)
+    out["single_multipole"]["variant"] = "multipole (Alg. M.1-M.3)"
+    log(f"[bench] single chain multipole {out['single_multipole']['value']:.1f} steps/s")
     if not args.no_batched:
         log("[bench] batched 256 chains, FP64")
         out["batched"] = run_batched(steps=args.batched_steps)
