@@ -65,6 +65,14 @@ extern "C" {
  * FMM_MC_ESTATE. FP64 only: combined with FMM_MC_MIXED it is rejected with
  * FMM_MC_EINVAL. Chains of one fmm_mc_run must all use the same variant. */
 #define FMM_MC_MULTIPOLE 0x2u
+/* Initialise the local expansions by direct P2L, Alg. L.3 (the paper's own
+ * initialisation, Sec. 3.2): every charge is added to the expansion of
+ * every cell in the interaction list of its cell on every level, images
+ * included, in place of the M2L pass. Always FP64; it also serves the
+ * re-setup. O(189 p^2 N L) work; the workspace holds extra chunk rows for
+ * it (fmm_mc_workspace_bytes with this flag). Not with FMM_MC_MULTIPOLE
+ * (FMM_MC_EINVAL). */
+#define FMM_MC_DIRECT_SETUP 0x4u
 
 typedef struct fmm_mc_ctx *fmm_mc_t;
 

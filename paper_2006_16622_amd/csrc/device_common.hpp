@@ -59,6 +59,7 @@ struct Chain {
   unsigned *sync;               // [4] sequence / done counters
   double *red;                  // partial sums of reductions
   double *part;                 // [512] per-workgroup partial sums of the whole-GPU run
+  double *dscr;                 // chunk rows of the direct P2L setup (null without it)
   double *stage;                // raw host positions (3N) then charges (N)
 };
 

@@ -208,7 +208,8 @@ struct Layout {
 
 enum {
   O_PX, O_PY, O_PZ, O_PQ, O_LEAF, O_SLOT, O_BCNT, O_BID, O_BP, O_LD, O_MP, O_K, O_H,
-  O_DIP, O_U, O_STATUS, O_SCRATCH, O_MBOX, O_SYNC, O_RED, O_PART, O_STAGE, O_STATS, O_CHAIN, O_TILES, O_END
+  O_DIP, O_U, O_STATUS, O_SCRATCH, O_MBOX, O_SYNC, O_RED, O_PART, O_STAGE, O_STATS, O_CHAIN, O_TILES, O_DSCR,
+  O_END
 };
 
 int bin_capacity(int64_t n, int levels) {
@@ -232,7 +233,16 @@ void append_m2l_tiles(std::vector<int4> &out, int chain, int levels) {
       out.push_back(make_int4(chain, oc, (int)f, (int)std::min<long long>(M2L_TT, T - f)));
 }
 
-void make_layout(int64_t n, int levels, int p, Layout &ly) {
+// chunk rows the direct P2L setup needs: the largest level below the leaves
+long long direct_rows(int levels) {
+  const int L = levels + 1;
+  long long rows = 0;
+  for (int l = 2; l < L; ++l)
+    if (p2l_chunks(L, l) > 1) rows = std::max(rows, (1LL << (3 * (l - 1))) * p2l_chunks(L, l));
+  return rows;
+}
+
+void make_layout(int64_t n, int levels, int p, uint32_t flags, Layout &ly) {
   const int C = (p + 1) * (p + 1), Cs = pad_cs(C), L = levels + 1;
   const int64_t nleaf = 1LL << (3 * levels);
   int64_t ncell_ld = 0, ncell_mp = 0;
@@ -264,6 +274,7 @@ void make_layout(int64_t n, int levels, int p, Layout &ly) {
   sz[O_STATS] = 8 * 64;
   sz[O_CHAIN] = sizeof(Chain);
   sz[O_TILES] = sizeof(int4) * (size_t)m2l_tiles(levels);
+  sz[O_DSCR] = (flags & FMM_MC_DIRECT_SETUP) ? 8 * (size_t)direct_rows(levels) * Cs : 0;
   size_t o = 0;
   for (int i = 0; i < O_END; ++i) {
     ly.off[i] = o;
@@ -328,6 +339,7 @@ struct SetupLaunch {
   bool restage = false;
   bool fp32_m2l = false;
   bool multipole = false;  // the multipole-based variant: no M2L
+  bool direct = false;     // direct P2L (Alg. L.3) in place of M2L
   int m2l_rows = 0;  // 96 or 192 (0: 96)
   int energy_mode = 2;
   hipEvent_t e1 = nullptr, e2 = nullptr;
@@ -371,7 +383,19 @@ int enqueue_setup(const SetupLaunch &S) {
   for (int l = S.max_levels; l >= 1; --l)
     hipLaunchKernelGGL(k_m2m, dim3(1 << (3 * (l - 1)), nc), dim3(256), 0, st, S.chains, tb, l);
   if (S.e1) HIPCHK(hipEventRecord(S.e1, st));
-  if (!S.multipole) launch_m2l(S);
+  if (S.direct) {
+    for (int l = 2; l <= S.max_levels + 1; ++l) {
+      const long long nt = 1LL << (3 * (l - 1));
+      const int nch = p2l_chunks(S.max_levels + 1, l);  // the most chunks any chain of the batch has
+      with_variant(variant_of(S.p), [&](auto gs, auto pm) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l_direct<decltype(gs)::value, decltype(pm)::value>),
+                           dim3((unsigned)(nt * nch), nc), dim3(NT), shm, st, S.chains, tb, l);
+      });
+      if (nch > 1) hipLaunchKernelGGL(k_p2l_reduce, dim3((unsigned)nt, nc), dim3(256), 0, st, S.chains, tb, l);
+    }
+  } else if (!S.multipole) {
+    launch_m2l(S);
+  }
   if (S.e2) HIPCHK(hipEventRecord(S.e2, st));
   hipLaunchKernelGGL(k_lattice_init, dim3(1, nc), dim3(NT), 0, st, S.chains, tb);
   with_variant(variant_of(S.p), [&](auto gs, auto pm) {
@@ -404,6 +428,7 @@ SetupLaunch single_launch(fmm_mc_ctx *h) {
   S.tb = &h->tables->tabs;
   S.fp32_m2l = (h->flags & FMM_MC_MIXED) != 0;
   S.multipole = (h->flags & FMM_MC_MULTIPOLE) != 0;
+  S.direct = (h->flags & FMM_MC_DIRECT_SETUP) != 0;
   S.m2l_rows = h->m2l_rows;
   return S;
 }
@@ -446,10 +471,9 @@ bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]
 extern "C" {
 
 int fmm_mc_workspace_bytes(int64_t n, int levels, int p, uint32_t flags, size_t *bytes) {
-  (void)flags;
   if (!bytes || n < 2 || levels < 1 || levels > LEVELS_MAX || p < 0 || p > PMAX) return FMM_MC_EINVAL;
   Layout ly;
-  make_layout(n, levels, p, ly);
+  make_layout(n, levels, p, flags, ly);
   *bytes = ly.total;
   return FMM_MC_OK;
 }
@@ -463,8 +487,8 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
     return FMM_MC_EINVAL;
   if (!(box > 0.0) || !std::isfinite(box)) return FMM_MC_EINVAL;
   if (((uintptr_t)dev_ws) % 256) return FMM_MC_EINVAL;
-  if ((flags & ~(FMM_MC_MIXED | FMM_MC_MULTIPOLE)) ||
-      ((flags & FMM_MC_MIXED) && (flags & FMM_MC_MULTIPOLE)))
+  if ((flags & ~(FMM_MC_MIXED | FMM_MC_MULTIPOLE | FMM_MC_DIRECT_SETUP)) ||
+      ((flags & FMM_MC_MULTIPOLE) && (flags & (FMM_MC_MIXED | FMM_MC_DIRECT_SETUP))))
     return FMM_MC_EINVAL;
   double qs = 0.0, qa = 0.0;
   for (int64_t i = 0; i < n; ++i) {
@@ -474,7 +498,7 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
   }
   if (std::fabs(qs) > 1e-12 * qa) return FMM_MC_ENONNEUTRAL;
   Layout ly;
-  make_layout(n, levels, p, ly);
+  make_layout(n, levels, p, flags, ly);
   if (ws_bytes < ly.total) return FMM_MC_ENOMEM;
   auto *h = new (std::nothrow) fmm_mc_ctx();
   if (!h) return FMM_MC_ENOMEM;
@@ -555,6 +579,7 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
   ch.sync = (unsigned *)(w + ly.off[O_SYNC]);
   ch.red = (double *)(w + ly.off[O_RED]);
   ch.part = (double *)(w + ly.off[O_PART]);
+  ch.dscr = (flags & FMM_MC_DIRECT_SETUP) ? (double *)(w + ly.off[O_DSCR]) : nullptr;
   ch.stage = (double *)(w + ly.off[O_STAGE]);
   h->d_chain = (Chain *)(w + ly.off[O_CHAIN]);
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
@@ -1145,6 +1170,7 @@ static Chain rebase_chain(const Chain &c, const char *from, char *to) {
   r.sync = rebase(c.sync, from, to);
   r.red = rebase(c.red, from, to);
   r.part = rebase(c.part, from, to);
+  r.dscr = rebase(c.dscr, from, to);
   r.stage = rebase(c.stage, from, to);
   return r;
 }
@@ -1176,9 +1202,10 @@ int fmm_mc_autotune(fmm_mc_t h, int64_t steps, double beta, double max_step, fmm
   // (a) M2L output rows per workgroup, timed on the clone (3 launches each)
   const int rows[2] = {96, 192};
   const bool mp = (h->flags & FMM_MC_MULTIPOLE) != 0;
+  const bool no_m2l = mp || (h->flags & FMM_MC_DIRECT_SETUP);  // no M2L pass to tune
   double best = 1e300;
-  t.m2l_rows = mp ? 96 : 192;  // the multipole-based variant has no M2L
-  for (int k = 0; k < 2 && !rc && !mp; ++k) {
+  t.m2l_rows = no_m2l ? 96 : 192;
+  for (int k = 0; k < 2 && !rc && !no_m2l; ++k) {
     SetupLaunch S = single_launch(&sh);
     S.m2l_rows = rows[k];
     launch_m2l(S);

@@ -338,6 +338,96 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
   }
 }
 
+// Direct P2L initialisation, Alg. L.3, ordered by target: the relation
+// "beta lies in IL(alpha)" is symmetric (with the image offset negated), so
+// the local expansion of cell beta on level l is the sum, over the 189 cells
+// alpha of IL(beta) (images included), of the P2L of every charge of alpha
+// at the centre of beta. The items of a target are the pairs (offset k,
+// leaf j below alpha), 189 * 8^(L-l) of them; they are cut into chunks of
+// P2L_CHUNK items, and one workgroup forms one chunk: its lane groups take
+// the items in turn, sum their charges' terms in registers, and the groups'
+// sums are added in a fixed order. A target with one chunk is written to
+// its row directly; otherwise each chunk goes to the chain's scratch rows,
+// and k_p2l_reduce adds the chunks in order.
+constexpr int P2L_CHUNK = 1024;
+__host__ __device__ inline long long p2l_items(int L, int l) { return 189LL << (3 * (L - l)); }
+__host__ __device__ inline int p2l_chunks(int L, int l) {
+  return (int)((p2l_items(L, l) + P2L_CHUNK - 1) / P2L_CHUNK);
+}
+
+template <int GS, int PM>
+__global__ void __launch_bounds__(WG_SETUP) k_p2l_direct(const Chain *chains, Tabs tb, int l) {
+  constexpr int NG = WG_SETUP / GS;
+  extern __shared__ double lds[];
+  const Chain &ch = chains[blockIdx.y];
+  if (l > ch.L) return;
+  const int n = 1 << (l - 1), sh = ch.L - l, m = 1 << sh, nL = 1 << (ch.L - 1);
+  const int nch = p2l_chunks(ch.L, l);
+  const long long ntarget = 1LL << (3 * (l - 1));
+  if ((long long)blockIdx.x >= ntarget * nch) return;
+  const int target = blockIdx.x / nch, chunk = blockIdx.x % nch;
+  const int g = threadIdx.x / GS, lane = threadIdx.x % GS, Cs = tb.Cs, C = tb.C;
+  const double a = ch.a, h = a / n;
+  const int c[3] = {target % n, (target / n) % n, target / (n * n)};
+  const int oc = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
+  const long long it0 = (long long)chunk * P2L_CHUNK;
+  const long long it1 = it0 + P2L_CHUNK < p2l_items(ch.L, l) ? it0 + P2L_CHUNK : p2l_items(ch.L, l);
+  ColSum<PM> cs;
+  cs.zero();
+  for (long long it = it0 + g; it < it1; it += NG) {
+    const int k = (int)(it >> (3 * sh)), j = (int)(it & ((1LL << (3 * sh)) - 1));
+    const int8_t *o = tb.il_off + (oc * 189 + k) * 3;
+    const int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
+    int leaf[3];
+    double shift[3];
+    for (int d = 0; d < 3; ++d) {
+      const int s = imod(b[d], n);
+      shift[d] = ifloordiv(b[d], n) * a;
+      leaf[d] = s * m;
+    }
+    leaf[0] += j % m;
+    leaf[1] += (j / m) % m;
+    leaf[2] += j / (m * m);
+    const int lf = lin3(nL, leaf[0], leaf[1], leaf[2]);
+    const int cnt = ch.bin_cnt[lf];
+    for (int t = 0; t < cnt; ++t) {
+      const double4 pj = ch.bin_p[(size_t)lf * ch.B + t];
+      group_harmonics_sum<GS, PM, 2>(lane, tb, tb.rec, (pj.x + shift[0] - (c[0] + 0.5) * h) / h,
+                                     (pj.y + shift[1] - (c[1] + 0.5) * h) / h,
+                                     (pj.z + shift[2] - (c[2] + 0.5) * h) / h, pj.w, cs);
+    }
+  }
+  double *buf = lds + (size_t)g * Cs;
+  for (int s = lane; s < Cs; s += GS) buf[s] = 0.0;
+  __builtin_amdgcn_wave_barrier();
+  flush_cols<PM, false>(lane, tb, cs, buf);
+  __syncthreads();
+  double *dst = nch == 1 ? ch.Ld + ch.ld_off[l] + (size_t)target * Cs
+                         : ch.dscr + ((size_t)target * nch + chunk) * Cs;
+  for (int s = threadIdx.x; s < C; s += WG_SETUP) {
+    double v = 0.0;
+    for (int gg = 0; gg < NG; ++gg) v += lds[(size_t)gg * Cs + s];
+    dst[s] = v;
+  }
+}
+
+// the chunks of each target of level l added in order into its row
+__global__ void k_p2l_reduce(const Chain *chains, Tabs tb, int l) {
+  const Chain &ch = chains[blockIdx.y];
+  if (l > ch.L) return;
+  const int nch = p2l_chunks(ch.L, l);
+  const long long ntarget = 1LL << (3 * (l - 1));
+  if (nch == 1 || (long long)blockIdx.x >= ntarget) return;
+  const int target = blockIdx.x, Cs = tb.Cs;
+  double *row = ch.Ld + ch.ld_off[l] + (size_t)target * Cs;
+  const double *src = ch.dscr + (size_t)target * nch * Cs;
+  for (int s = threadIdx.x; s < tb.C; s += blockDim.x) {
+    double v = 0.0;
+    for (int k = 0; k < nch; ++k) v += src[(size_t)k * Cs + s];
+    row[s] = v;
+  }
+}
+
 // K = level-1 multipole (about the box centre, scaled by a); H = R(K);
 // dipole D = sum q r (one workgroup per chain)
 __global__ void k_lattice_init(const Chain *chains, Tabs tb) {
