@@ -195,7 +195,7 @@ def cpu_baseline(wl, nu, nprop=8000, nacc=1000):
         ew.accept(i, r)
     tae = (time.perf_counter() - t0) / 100
     errs = {}
-    for name, flags in (("f64", 0), ("mixed", FMM_MC_MIXED)):
+    for name, flags in (("f64", 0), ("mixed", FMM_MC_MIXED), ("direct_setup", 4), ("multipole", 2)):
         ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
         de = np.array([ch.propose(i, r) for i, r in moves])
         ch.close()
@@ -203,7 +203,8 @@ def cpu_baseline(wl, nu, nprop=8000, nacc=1000):
     out["ewald"] = {"value": 1.0 / (tpe + nu * tae), "unit": "MH steps/s", "cores": 1, "kind": "oracle",
                     "setup_s": t_ew_setup, "t_prop_ms": tpe * 1e3, "t_acc_ms": tae * 1e3}
     out["dE_rel_rms_err_vs_ewald"] = errs
-    out["dE_err_sample"] = "200 proposals of the Philox stream from the initial rock-salt state, p = 12"
+    out["dE_err_sample"] = ("200 proposals of the Philox stream from the initial rock-salt state, p = 12; "
+                            "direct_setup: local expansions by Alg. L.3; multipole: Alg. M.1-M.3")
     return out
 
 
@@ -441,6 +442,14 @@ def main():
     log("[bench] single chain, mixed precision")
     out["single_mixed"] = run_single_mixed(wl, args.steps, args.warmup)
     log(f"[bench] single chain mixed {out['single_mixed']['value']:.1f} steps/s")
+    log("[bench] direct P2L setup (Alg. L.3)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chd = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=4)
+    torch.cuda.synchronize()
+    out["setup_direct"] = {"wall_ms": (time.perf_counter() - t0) * 1e3, "p2l_ms": chd.last_timing()[1]}
+    chd.close()
+    log(f"[bench] direct setup {out['setup_direct']['wall_ms']:.1f} ms (P2L {out['setup_direct']['p2l_ms']:.2f} ms)")
     log("[bench] single chain, multipole-based variant")
     out["single_multipole"] = run_single_variant(wl, args.steps // 4, args.warmup, flags=2, tune=True)
     out["single_multipole"]["variant"] = "multipole (Alg. M.1-M.3)"

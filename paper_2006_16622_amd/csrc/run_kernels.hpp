@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
   constexpr int NT = WG_SINGLE;
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
-  __shared__ Move mv;
+  __shared__ Move mvs[2];  // the move of this step and the next (workgroup 0); helpers use mvs[0]
   __shared__ NextDraw nd;
   __shared__ int s_flag, s_acc;
   __shared__ unsigned s_seq;
@@ -541,41 +541,46 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
     int status = 0;
     unsigned num = 0;  // move number of this launch
     uint64_t tick_prop = 0, tick_acc = 0, tick_wait = 0;
-    bool prev_acc = false;
-    int prev_idx = -1;
-    double prev_rn[3] = {0, 0, 0};
     const int64_t s0 = rp.first ? rp.first[0] : 0;
     int64_t acc_launch = 0;
-    if (t == 0 && s0 < rp.steps) draw_into(rp, c, s0, ch, D, nd);
-    __syncthreads();
-    for (int64_t step = s0; step < rp.steps; ++step) {
-      uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
-      ++num;
+    int cur = 0;  // mvs[cur]: the move of this step, located and posted
+    // the move of step s0 (no move accepted before it in this launch)
+    auto next_move = [&](bool acc, int prev_idx, const double *prev_rn, int slot) {
       if (t == 0) {
-        move_from_draw(rp, ch, nd, prev_acc, prev_idx, prev_rn, mv);
+        move_from_draw(rp, ch, nd, acc, prev_idx, prev_rn, mvs[slot]);
         s_u = nd.u;
       }
       __syncthreads();
-      locate_move_par(ch, mv);
+      locate_move_par(ch, mvs[slot]);
       __syncthreads();
+      ++num;
+      if (t == 0 && G > 1) {
+        const auto sl = glb(mb) + 8 * (num & 1);
+        const Move &m = mvs[slot];
+        sl[0] = (double)m.idx;
+        sl[1] = m.q;
+        for (int k = 0; k < 3; ++k) {
+          sl[2 + k] = m.r[k];
+          sl[5 + k] = m.rn[k];
+        }
+        st_release(mvseq, num);
+      }
+    };
+    if (s0 < rp.steps) {
+      if (t == 0) draw_into(rp, c, s0, ch, D, nd);
+      __syncthreads();
+      const double none[3] = {0, 0, 0};
+      next_move(false, -1, none, 0);
+    }
+    for (int64_t step = s0; step < rp.steps; ++step) {
+      uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
+      const Move &mv = mvs[cur];
       const double u = s_u;
-      ProposeOut po = propose_wg<GS, PM, double, false>(
-          ch, tb, mv, sm,
-          [&](int lane) {
-            if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
-          },
-          [&](int lane) {
-            if (lane == 0 && G > 1) {
-              const auto slot = glb(mb) + 8 * (num & 1);
-              slot[0] = (double)mv.idx;
-              slot[1] = mv.q;
-              for (int k = 0; k < 3; ++k) {
-                slot[2 + k] = mv.r[k];
-                slot[5 + k] = mv.rn[k];
-              }
-              st_release(mvseq, num);
-            }
-          });
+      // near field, self-image, lattice and tin-foil terms; the last
+      // wavefront fetches the next draw meanwhile
+      ProposeOut po = propose_wg<GS, PM, double, false>(ch, tb, mv, sm, [&](int lane) {
+        if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
+      });
       uint64_t t_w = __builtin_amdgcn_s_memrealtime();
       if (G > 1) {
         // the helpers' partial sums, added in helper order
@@ -628,14 +633,18 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
         }
       }
       __syncthreads();
-      prev_acc = s_acc;
-      prev_idx = mv.idx;
-      for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
-      if (prev_acc) {
+      const bool acc = s_acc;
+      const bool last = acc && rp.acc_limit && acc_launch + 1 >= rp.acc_limit;
+      if (acc) {
+        // the multipoles first: the next move may be posted only when every
+        // thread's stores are released
         accept_mp_wg<GS, PM, NT>(ch, tb, mv, sm.rec);
-        // each thread releases its own multipole stores; the next move is
-        // posted after the barriers of the bookkeeping
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      }
+      // the next move is posted before this move's bookkeeping, so the
+      // helpers evaluate its far field while the bookkeeping runs
+      if (step + 1 < rp.steps && !last) next_move(acc, mv.idx, mv.rn, cur ^ 1);
+      if (acc) {
         int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, dE, sm);
         if (t == 0) {
           nacc += 1;
@@ -646,8 +655,12 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
           status = -7;
           break;
         }
-        if (rp.acc_limit && ++acc_launch >= rp.acc_limit) break;
+        ++acc_launch;
+        if (last) break;
+      } else {
+        tick_prop += __builtin_amdgcn_s_memrealtime() - t_1;  // forming the next move
       }
+      cur ^= 1;
       // every step ends at a barrier (see the helper loop)
       __syncthreads();
     }
@@ -673,6 +686,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
   // uniform over each wavefront) and every iteration ends at a barrier, so
   // no per-thread branch at the end of one iteration can be merged by the
   // compiler with the wait of the next.
+  Move &mv = mvs[0];
   unsigned cur = 0;
   while (true) {
     if (t < 64) {
