@@ -533,20 +533,24 @@ __device__ bool accept_block_compute(const Chain &ch, const Tabs &tb, const Move
 }
 
 // write the rows formed by accept_block_compute (all threads; the caller
-// synchronises the workgroup between the two)
+// synchronises the workgroup between the two). The stores are device-coherent
+// (agent scope): they are written through the XCD's L2, so the release that
+// publishes them finds few dirty lines to write back; with plain stores the
+// release of every helper wrote back the rows of all helpers on its XCD.
 template <int GS, int NT>
 __device__ __forceinline__ void accept_block_store(const Tabs &tb, bool coarse, const double *out,
                                                    double *const *dst) {
   const int C = tb.C, Cs = tb.Cs, t = threadIdx.x;
   if (coarse) {
     const auto row = glb(dst[0]);
-    for (int k = t; k < C; k += NT) row[k] = out[k];
+    for (int k = t; k < C; k += NT) __hip_atomic_store(row + k, out[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
   const int g = t / GS, lane = t % GS;
   if (dst[g]) {
     const auto row = glb(dst[g]);
-    for (int k = lane; k < C; k += GS) row[k] = out[(size_t)g * Cs + k];
+    for (int k = lane; k < C; k += GS)
+      __hip_atomic_store(row + k, out[(size_t)g * Cs + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
