@@ -84,6 +84,7 @@ def _load():
         "orc_setup_direct": (None, [vp]),
         "orc_setup_none": (None, [vp]),
         "orc_setup_multipole": (None, [vp, ctypes.c_int]),
+        "orc_set_free_space": (None, [vp]),
         "orc_get_multipole": (None, [vp, ctypes.c_int, ctypes.c_int, _dp]),
         "orc_propose": (ctypes.c_double, [vp, ctypes.c_int, _dp]),
         "orc_accept": (None, [vp, ctypes.c_int, _dp]),
@@ -258,9 +259,13 @@ class Multilevel:
     (Alg. M.1-M.3, multipoles formed directly per level);
     ``"multipole_upward"`` is the same variant with the multipoles formed by
     the FMM upward pass (P2M, M2M).
+
+    ``free_space=True`` selects free-space boundary conditions (Sec. 3.4):
+    no images, no lattice or tin-foil terms, a move out of the box has
+    dE = +inf.
     """
 
-    def __init__(self, pos, q, box: float, depth: int, p: int, setup: str = "fmm"):
+    def __init__(self, pos, q, box: float, depth: int, p: int, setup: str = "fmm", free_space: bool = False):
         lib = _load()
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
@@ -269,7 +274,11 @@ class Multilevel:
         self.depth = int(depth)
         self.p = int(p)
         self.C = ncoef(p)
+        if free_space and not ((pos >= 0).all() and (pos < box).all()):
+            raise ValueError("free space: every position must lie in [0, box)")
         self._h = lib.orc_create(self.N, _d(pos), _d(q), self.box, self.depth, self.p)
+        if free_space:
+            lib.orc_set_free_space(self._h)
         if setup == "fmm":
             lib.orc_setup_fmm(self._h, 0)
         elif setup == "lazy":

@@ -525,6 +525,7 @@ typedef struct {
   double dip[3];   /* dipole sum q_i r_i (wrapped positions) */
   int lazy;
   int multipole;   /* the multipole-based variant of Sec. 3.3: Mp is the live state */
+  int free_space;  /* free-space boundary conditions (Sec. 3.4): no images, no lattice */
   move_rec *log;   /* lazy mode: accepted moves since setup */
   int nlog, caplog;
 } orc_t;
@@ -537,6 +538,18 @@ static void cell_centre(const orc_t *st, int l, const int *c, double *R) {
 }
 
 static int cell_lin(int n, const int *c) { return c[0] + n * (c[1] + n * c[2]); }
+
+/* is the (unwrapped) cell b of a level with n cells per side a cell of the
+ * box itself? Under free-space boundary conditions the box is the whole
+ * domain: a cell outside it holds nothing. */
+static int in_box(int n, const int *b) {
+  return b[0] >= 0 && b[0] < n && b[1] >= 0 && b[1] < n && b[2] >= 0 && b[2] < n;
+}
+
+/* does x lie in the box [0,a)^3? */
+static int point_in_box(const double *x, double a) {
+  return x[0] >= 0.0 && x[0] < a && x[1] >= 0.0 && x[1] < a && x[2] >= 0.0 && x[2] < a;
+}
 
 static void locate(const orc_t *st, int l, const double *x, int *c) {
   int n = nside(l);
@@ -597,6 +610,15 @@ orc_t *orc_create(int N, const double *pos, const double *q, double a, int d, in
   return st;
 }
 
+/* Free-space boundary conditions (Sec. 3.4): the box [0,a)^3 is the whole
+ * domain. Interaction lists and near regions keep only cells inside the box
+ * (so the lists of levels 1 and 2 are empty), the self correction keeps only
+ * the charge's own old position, and there is no lattice or tin-foil term.
+ * Positions are not wrapped; a move out of the box has dE = +inf. To be
+ * called right after orc_create, before any setup, with every position
+ * inside the box. */
+void orc_set_free_space(orc_t *st) { st->free_space = 1; }
+
 void orc_destroy(orc_t *st) {
   if (!st) return;
   int nL = nside(st->L);
@@ -631,7 +653,7 @@ static void init_lattice(orc_t *st) {
     orc_p2e(st->p, st->q[i], &st->pos[3 * i], R1, (double *)st->E);
     for (int k = 0; k < 3; ++k) st->dip[k] += st->q[i] * st->pos[3 * i + k];
   }
-  orc_lattice_sums(2 * st->p, st->a, 12, (double *)st->S);
+  if (!st->free_space) orc_lattice_sums(2 * st->p, st->a, 12, (double *)st->S);
 }
 
 /* multipoles of every cell on levels 2..L: P2M on the leaves, then M2M
@@ -675,6 +697,7 @@ static void m2l_cell(orc_t *st, int l, const int *c, cplx *out) {
   int cnt = orc_il_offsets(oct, off);
   for (int i = 0; i < cnt; ++i) {
     int b[3] = {c[0] + off[3 * i], c[1] + off[3 * i + 1], c[2] + off[3 * i + 2]};
+    if (st->free_space && !in_box(n, b)) continue;
     int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
     double dv[3] = {off[3 * i] * h, off[3 * i + 1] * h, off[3 * i + 2] * h};
     orc_m2l(st->p, (double *)&st->Mp[l][(size_t)cell_lin(n, s) * st->C], dv, (double *)out);
@@ -691,6 +714,7 @@ static void p2l_into_cell(orc_t *st, int l, int target, double q, const double *
   int cnt = orc_il_offsets(oct, off);
   for (int i = 0; i < cnt; ++i) {
     int b[3] = {a[0] + off[3 * i], a[1] + off[3 * i + 1], a[2] + off[3 * i + 2]};
+    if (st->free_space && !in_box(n, b)) continue;
     int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
     if (cell_lin(n, s) != target) continue;
     double R[3];
@@ -780,6 +804,7 @@ void orc_setup_direct(orc_t *st) {
       int cnt = orc_il_offsets(oct, off);
       for (int j = 0; j < cnt; ++j) {
         int b[3] = {a[0] + off[3 * j], a[1] + off[3 * j + 1], a[2] + off[3 * j + 2]};
+        if (st->free_space && !in_box(n, b)) continue;
         int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
         double R[3] = {(b[0] + 0.5) * h, (b[1] + 0.5) * h, (b[2] + 0.5) * h};
         orc_p2l(st->p, st->q[i], &st->pos[3 * i], R,
@@ -834,6 +859,7 @@ static double m2p_far(orc_t *st, const double *x) {
     int cnt = orc_il_offsets(oct, off);
     for (int j = 0; j < cnt; ++j) {
       int b[3] = {a[0] + off[3 * j], a[1] + off[3 * j + 1], a[2] + off[3 * j + 2]};
+      if (st->free_space && !in_box(n, b)) continue;
       int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
       double R[3] = {(b[0] + 0.5) * h, (b[1] + 0.5) * h, (b[2] + 0.5) * h};
       acc += orc_m2p(st->p, (double *)&st->Mp[l][(size_t)cell_lin(n, s) * st->C], x, R);
@@ -858,6 +884,7 @@ static double near_sum(orc_t *st, const double *x, int skip_id, int skip_all_ima
     for (int ey = -1; ey <= 1; ++ey)
       for (int ex = -1; ex <= 1; ++ex) {
         int b[3] = {c[0] + ex, c[1] + ey, c[2] + ez};
+        if (st->free_space && !in_box(n, b)) continue;
         int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
         int w[3] = {ifloordiv(b[0], n), ifloordiv(b[1], n), ifloordiv(b[2], n)};
         cell_list *cl = &st->leaf[cell_lin(n, s)];
@@ -898,7 +925,9 @@ static double lattice_energy(const orc_t *st, const cplx *K, const cplx *E) {
  * lists of both cells on every level (Alg. M.1). */
 double orc_propose(orc_t *st, int k, const double *newpos_in) {
   double a = st->a, q = st->q[k], rn[3], *r = &st->pos[3 * k];
-  for (int i = 0; i < 3; ++i) rn[i] = orc_wrap(newpos_in[i], a);
+  for (int i = 0; i < 3; ++i) rn[i] = st->free_space ? newpos_in[i] : orc_wrap(newpos_in[i], a);
+  /* free space: a move out of the box is never taken */
+  if (st->free_space && !point_in_box(rn, a)) return INFINITY;
   double dE = 0.0;
   /* long range, multipole-based variant (Alg. M.1): the expansions of the
    * interaction lists of both cells on every level */
@@ -920,16 +949,20 @@ double orc_propose(orc_t *st, int k, const double *newpos_in) {
   double dnew = near_sum(st, rn, k, 1, skip_nu);
   double dold = near_sum(st, r, k, 0, NULL);
   dE += q * (dnew - dold);
-  /* periodic self-interaction correction (Sec. 3.4) */
+  /* periodic self-interaction correction (Sec. 3.4); in free space only
+   * the charge's own old position (nu = 0) is subtracted */
   double self = 0.0;
   for (int nz = -1; nz <= 1; ++nz)
     for (int ny = -1; ny <= 1; ++ny)
       for (int nx = -1; nx <= 1; ++nx) {
         if (skip_nu[(nx + 1) + 3 * (ny + 1) + 9 * (nz + 1)]) continue;
+        if (st->free_space && (nx || ny || nz)) continue;
         double dv[3] = {rn[0] - (r[0] + a * nx), rn[1] - (r[1] + a * ny), rn[2] - (r[2] + a * nz)};
         self += q * q / sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
       }
-  dE += -self + q * q / a * orc_self_image_constant();
+  dE += -self;
+  if (st->free_space) return dE;
+  dE += q * q / a * orc_self_image_constant();
   /* far lattice (Sec. 3.4, with the factor 1/2 of a pair energy) */
   double R1c[3] = {0.5 * a, 0.5 * a, 0.5 * a};
   cplx *K2 = (cplx *)malloc(sizeof(cplx) * st->C), *E2 = (cplx *)malloc(sizeof(cplx) * st->C);
@@ -960,9 +993,10 @@ double orc_propose(orc_t *st, int k, const double *newpos_in) {
 void orc_accept(orc_t *st, int k, const double *newpos_in) {
   double a = st->a, q = st->q[k], rn[3], r[3];
   for (int i = 0; i < 3; ++i) {
-    rn[i] = orc_wrap(newpos_in[i], a);
+    rn[i] = st->free_space ? newpos_in[i] : orc_wrap(newpos_in[i], a);
     r[i] = st->pos[3 * k + i];
   }
+  if (st->free_space && !point_in_box(rn, a)) return; /* never taken */
   /* multipole-based variant (Alg. M.2): the charge leaves the multipole
    * expansion of its old cell and joins that of its new cell, per level */
   for (int l = st->L; l >= 2 && st->multipole; --l) {
@@ -987,6 +1021,7 @@ void orc_accept(orc_t *st, int k, const double *newpos_in) {
       int cnt = orc_il_offsets(oct, off);
       for (int j = 0; j < cnt; ++j) {
         int b[3] = {c[0] + off[3 * j], c[1] + off[3 * j + 1], c[2] + off[3 * j + 2]};
+        if (st->free_space && !in_box(n, b)) continue;
         int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
         int lin = cell_lin(n, s);
         if (st->lazy && !st->ready[l][lin]) continue; /* formed later from the log */
@@ -1037,6 +1072,7 @@ double orc_energy(orc_t *st) {
     phi += near_sum(st, r, i, 0, NULL);
     U += 0.5 * st->q[i] * phi;
   }
+  if (st->free_space) return U;
   U += lattice_energy(st, st->K, st->E);
   double V = st->a * st->a * st->a;
   U += -2.0 * M_PI / (3.0 * V) *
@@ -1075,7 +1111,8 @@ int64_t orc_run(orc_t *st, uint64_t seed, uint64_t chain, int64_t t0, int64_t ns
     int64_t idx;
     double delta[3], u, rn[3];
     orc_draw(seed, chain, (uint64_t)t, st->N, D, &idx, delta, &u);
-    for (int k = 0; k < 3; ++k) rn[k] = orc_wrap(st->pos[3 * idx + k] + delta[k], st->a);
+    for (int k = 0; k < 3; ++k)
+      rn[k] = st->free_space ? st->pos[3 * idx + k] + delta[k] : orc_wrap(st->pos[3 * idx + k] + delta[k], st->a);
     double dE = orc_propose(st, (int)idx, rn);
     int acc = u < exp(-beta * dE);
     if (acc) {
