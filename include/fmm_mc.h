@@ -73,6 +73,16 @@ extern "C" {
  * it (fmm_mc_workspace_bytes with this flag). Not with FMM_MC_MULTIPOLE
  * (FMM_MC_EINVAL). */
 #define FMM_MC_DIRECT_SETUP 0x4u
+/* Free-space boundary conditions (Sec. 3.4): the box [0, box)^3 is the whole
+ * domain. No periodic images: interaction lists and near regions keep only
+ * cells inside the box (the lists of levels 1 and 2 are empty), the self
+ * correction keeps only the charge's own old position, and there is no
+ * far-lattice or tin-foil term. Positions are not wrapped: every initial
+ * position must lie inside the box (else FMM_MC_EINVAL), a proposal out of
+ * the box has dE = +inf (it is never accepted by fmm_mc_run), and
+ * fmm_mc_accept of such a move returns FMM_MC_EINVAL. Combines with every
+ * other flag. */
+#define FMM_MC_FREE_SPACE 0x8u
 
 typedef struct fmm_mc_ctx *fmm_mc_t;
 

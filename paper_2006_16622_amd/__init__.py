@@ -7,5 +7,5 @@ The work runs in hand-written HIP kernels behind the C ABI of
 arguments (``binding``) and uses PyTorch for device memory and streams.
 There is no CPU fallback: without the built library every call raises.
 """
-from .binding import (FMM_MC_DIRECT_SETUP, FMM_MC_MIXED, FMM_MC_MULTIPOLE, FmmMcError, Chain, load_library, run_chains,  # noqa: F401
+from .binding import (FMM_MC_DIRECT_SETUP, FMM_MC_FREE_SPACE, FMM_MC_MIXED, FMM_MC_MULTIPOLE, FmmMcError, Chain, load_library, run_chains,  # noqa: F401
                       setup_batch, host_operator, workspace_bytes)

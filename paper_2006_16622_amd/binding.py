@@ -17,6 +17,7 @@ LIB_PATH = os.environ.get("FMM_MC_LIB", os.path.join(HERE, "libfmm_mc.so"))
 FMM_MC_MIXED = 0x1
 FMM_MC_MULTIPOLE = 0x2
 FMM_MC_DIRECT_SETUP = 0x4
+FMM_MC_FREE_SPACE = 0x8
 _ERRORS = {0: "ok", -1: "EINVAL", -2: "ERANGE", -3: "ENONNEUTRAL", -4: "ESINGULAR", -5: "ENOMEM",
            -6: "EDEVICE", -7: "EOVERFLOW", -8: "ESTATE"}
 

@@ -40,6 +40,7 @@ struct Tabs {
 struct Chain {
   int N, d, L, B;               // charges, depth, levels (d+1), bin capacity
   int mixed;
+  int free_space;               // free-space boundary conditions: no images, no lattice
   double a;                     // box side
   double inv_h[MAXL + 2];       // n_l / a on level l (cells per unit length), one IEEE division
   double *px, *py, *pz, *pq;    // particles by id (wrapped positions)

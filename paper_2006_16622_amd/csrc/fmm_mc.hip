@@ -466,6 +466,10 @@ int compute_energy(fmm_mc_ctx *h, double *U) {
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
+bool in_box(const double *v, double a) {
+  return v[0] >= 0.0 && v[0] < a && v[1] >= 0.0 && v[1] < a && v[2] >= 0.0 && v[2] < a;
+}
+
 }  // namespace
 
 extern "C" {
@@ -487,12 +491,14 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
     return FMM_MC_EINVAL;
   if (!(box > 0.0) || !std::isfinite(box)) return FMM_MC_EINVAL;
   if (((uintptr_t)dev_ws) % 256) return FMM_MC_EINVAL;
-  if ((flags & ~(FMM_MC_MIXED | FMM_MC_MULTIPOLE | FMM_MC_DIRECT_SETUP)) ||
+  if ((flags & ~(FMM_MC_MIXED | FMM_MC_MULTIPOLE | FMM_MC_DIRECT_SETUP | FMM_MC_FREE_SPACE)) ||
       ((flags & FMM_MC_MULTIPOLE) && (flags & (FMM_MC_MIXED | FMM_MC_DIRECT_SETUP))))
     return FMM_MC_EINVAL;
   double qs = 0.0, qa = 0.0;
+  const bool free_space = (flags & FMM_MC_FREE_SPACE) != 0;
   for (int64_t i = 0; i < n; ++i) {
     if (!finite3(pos + 3 * i) || !std::isfinite(q[i])) return FMM_MC_EINVAL;
+    if (free_space && !in_box(pos + 3 * i, box)) return FMM_MC_EINVAL;
     qs += q[i];
     qa += std::fabs(q[i]);
   }
@@ -542,6 +548,7 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
   ch.L = levels + 1;
   ch.B = ly.B;
   ch.mixed = (flags & FMM_MC_MIXED) ? 1 : 0;
+  ch.free_space = (flags & FMM_MC_FREE_SPACE) ? 1 : 0;
   ch.a = box;
   for (int l = 0; l <= MAXL + 1; ++l) ch.inv_h[l] = double(1LL << (l > 0 ? l - 1 : 0)) / box;
   ch.px = (double *)(w + ly.off[O_PX]);
@@ -755,6 +762,7 @@ int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
 int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *dE_in, double *dE_out) {
   if (!h || !h->ready) return FMM_MC_ESTATE;
   if (!new_pos || !finite3(new_pos)) return FMM_MC_EINVAL;
+  if ((h->flags & FMM_MC_FREE_SPACE) && !in_box(new_pos, h->box)) return FMM_MC_EINVAL;
   if (idx < 0 || idx >= h->n) return FMM_MC_ERANGE;
   double dE = 0.0;
   if (dE_in) {

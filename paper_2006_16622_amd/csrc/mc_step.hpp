@@ -161,7 +161,7 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     const int w = (fx + 1) + 3 * (fy + 1) + 9 * (fz + 1);
     const double sx = fx * a, sy = fy * a, sz = fz * a;
     const size_t base = (size_t)cell * B;
-    const int cnt = glb(ch.bin_cnt)[cell];
+    const int cnt = (ch.free_space && w != 13) ? 0 : glb(ch.bin_cnt)[cell];  // free space: no images
     int id = glb(ch.bin_id)[base + j0];
     double4 pj = ld_rec(ch.bin_p, base + j0);
     if (ee == 13 && j0 == 0) ints[side ? I_CNTNEW : I_CNTOLD] = cnt;
@@ -264,7 +264,7 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
   __syncthreads();
   // self-interaction with the old position's images (Sec. 3.4)
   double self = 0.0;
-  if (t < 27 && !((ints[I_MASK] >> t) & 1)) {
+  if (t < 27 && !((ints[I_MASK] >> t) & 1) && (!ch.free_space || t == 13)) {
     double sx = (t % 3 - 1) * a, sy = ((t / 3) % 3 - 1) * a, sz = (t / 9 - 1) * a;
     double dx = mv.rn[0] - (mv.r[0] + sx), dy = mv.rn[1] - (mv.r[1] + sy), dz = mv.rn[2] - (mv.r[2] + sz);
     self = q * q / sqrt(dx * dx + dy * dy + dz * dz);
@@ -283,12 +283,19 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     dE += q * (sm.vals[po + 1] - sm.vals[po]);
   }
   dE += q * (part[1] - part[0]);
-  dE += -part[2] + q * q / a * tb.self_const;
-  dE += q * (sm.vals[1] - sm.vals[0]) + 0.5 * part[3] / a;
-  double dr[3] = {mv.rn[0] - mv.r[0], mv.rn[1] - mv.r[1], mv.rn[2] - mv.r[2]};
-  double Ddot = sm.st[0] * dr[0] + sm.st[1] * dr[1] + sm.st[2] * dr[2];
-  double dd = dr[0] * dr[0] + dr[1] * dr[1] + dr[2] * dr[2];
-  dE += -2.0 * M_PI / (3.0 * a * a * a) * (2.0 * q * Ddot + q * q * dd);
+  dE += -part[2];
+  if (!ch.free_space) {
+    // periodic images of the moving charge, far lattice, tin-foil (Sec. 3.4)
+    dE += q * q / a * tb.self_const;
+    dE += q * (sm.vals[1] - sm.vals[0]) + 0.5 * part[3] / a;
+    double dr[3] = {mv.rn[0] - mv.r[0], mv.rn[1] - mv.r[1], mv.rn[2] - mv.r[2]};
+    double Ddot = sm.st[0] * dr[0] + sm.st[1] * dr[1] + sm.st[2] * dr[2];
+    double dd = dr[0] * dr[0] + dr[1] * dr[1] + dr[2] * dr[2];
+    dE += -2.0 * M_PI / (3.0 * a * a * a) * (2.0 * q * Ddot + q * q * dd);
+  } else if (!(mv.rn[0] >= 0.0 && mv.rn[0] < a && mv.rn[1] >= 0.0 && mv.rn[1] < a && mv.rn[2] >= 0.0 &&
+               mv.rn[2] < a)) {
+    dE = INFINITY;  // free space: a move out of the box is never taken
+  }
   out.dE = dE;
   out.singular = sing;
   __syncthreads();
@@ -312,13 +319,14 @@ __host__ __device__ inline int accept_blocks(int L, int NG) {
 }
 
 // is some image of stored cell s (on a level of n >= 8 cells per side) in the
-// interaction list of cell c? returns the image in b
-__device__ __forceinline__ bool image_in_il(const int s[3], const int c[3], int n, int b[3]) {
+// interaction list of cell c? returns the image in b. In free space only the
+// cell itself counts.
+__device__ __forceinline__ bool image_in_il(const int s[3], const int c[3], int n, int b[3], bool free_space) {
   int mx = 0;
   for (int k = 0; k < 3; ++k) {
     int lo = 2 * (c[k] >> 1) - 2;
     int v = lo + imod(s[k] - lo, n);
-    if (v >= lo + 6) return false;
+    if (v >= lo + 6 || (free_space && v != s[k])) return false;
     b[k] = v;
     int dd = v - c[k];
     dd = dd < 0 ? -dd : dd;
@@ -352,8 +360,9 @@ __device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, c
   const int8_t *o = il_off + (oc * 189 + k189) * 3;
   int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
   int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
+  if (ch.free_space && (b[0] != s[0] || b[1] != s[1] || b[2] != s[2])) return it;  // outside the box
   int b_other[3];
-  const bool other = image_in_il(s, co, n, b_other);
+  const bool other = image_in_il(s, co, n, b_other, ch.free_space);
   if (side == 1 && other) return it;  // owned by the old-side item
   it.active = 1;
   it.dst = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * tb.Cs;
@@ -373,11 +382,12 @@ __device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, c
 // s + n w, w in {-1,0,1}^3, lies in the interaction list of the old (side 0)
 // or new (side 1) cell. Computed by the GS lanes of a group.
 template <int GS>
-__device__ __forceinline__ uint64_t coarse_mask(const Move &mv, int l, const int s[3], int lane) {
+__device__ __forceinline__ uint64_t coarse_mask(const Move &mv, int l, const int s[3], int lane, bool free_space) {
   const int n = 1 << (l - 1);
   uint64_t m = 0;
   for (int cand = lane; cand < 54; cand += GS) {
     const int side = cand / 27, e = cand % 27;
+    if (free_space && e != 13) continue;  // images only under periodicity
     const int *c = side ? mv.c1[l] : mv.c0[l];
     const int w[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
     int mx = 0;
@@ -454,7 +464,7 @@ __device__ bool accept_block_compute(const Chain &ch, const Tabs &tb, const Move
     if (t < 64) {
       bool valid = false;
       int side = t / 27, e = t % 27;
-      if (t < 54) {
+      if (t < 54 && (!ch.free_space || e == 13)) {
         const int *c = side ? mv.c1[l] : mv.c0[l];
         int w[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
         int mx = 0;
@@ -585,7 +595,7 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
   {
     const int cell = g % 8, part = g / 8;
     const int s3[3] = {cell % 2, (cell / 2) % 2, cell / 4};
-    uint64_t m = coarse_mask<GS>(mv, 2, s3, lane);
+    uint64_t m = coarse_mask<GS>(mv, 2, s3, lane, ch.free_space);
     for (int k = lane; k < Cs; k += GS) buf[k] = 0.0;
     __builtin_amdgcn_wave_barrier();
     int idx = 0;
@@ -615,7 +625,7 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
         int k = lane + j * GS;
         old[j] = k < C ? dst[k] : 0.0;
       }
-      uint64_t m = coarse_mask<GS>(mv, 3, s3, lane);
+      uint64_t m = coarse_mask<GS>(mv, 3, s3, lane, ch.free_space);
       for (int k = lane; k < Cs; k += GS) buf[k] = 0.0;
       __builtin_amdgcn_wave_barrier();
       while (m) {

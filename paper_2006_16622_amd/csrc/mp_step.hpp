@@ -30,6 +30,8 @@ __device__ __forceinline__ double m2p_cell(const Chain &ch, const Tabs &tb, cons
   const int oc = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
   const int8_t *o = il_off + (oc * 189 + k) * 3;
   const int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
+  // free space: cells outside the box hold nothing (uniform over the group)
+  if (ch.free_space && (b[0] < 0 || b[0] >= n || b[1] < 0 || b[1] >= n || b[2] < 0 || b[2] >= n)) return 0.0;
   double v[3];
   for (int d = 0; d < 3; ++d) v[d] = (x[d] - (b[d] + 0.5) * h) / h;
   const auto src =

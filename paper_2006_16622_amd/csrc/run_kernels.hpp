@@ -88,7 +88,7 @@ __device__ __forceinline__ void move_from_draw(const RunParams &rp, const Chain 
   for (int k = 0; k < 3; ++k) {
     mv.r[k] = r[k];
     double rn_abs = rp.list_idx ? nd.d[k] : r[k] + nd.d[k];
-    mv.rn[k] = wrap_coord(rn_abs, ch.a);
+    mv.rn[k] = ch.free_space ? rn_abs : wrap_coord(rn_abs, ch.a);
   }
 }
 
@@ -749,9 +749,9 @@ __device__ __forceinline__ void move_direct(const Chain &ch, int64_t idx, double
     mv.r[0] = glb(ch.px)[idx];
     mv.r[1] = glb(ch.py)[idx];
     mv.r[2] = glb(ch.pz)[idx];
-    mv.rn[0] = wrap_coord(x, ch.a);
-    mv.rn[1] = wrap_coord(y, ch.a);
-    mv.rn[2] = wrap_coord(z, ch.a);
+    mv.rn[0] = ch.free_space ? x : wrap_coord(x, ch.a);
+    mv.rn[1] = ch.free_space ? y : wrap_coord(y, ch.a);
+    mv.rn[2] = ch.free_space ? z : wrap_coord(z, ch.a);
   }
   __syncthreads();
   locate_move_par(ch, mv);

@@ -246,9 +246,11 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
 #pragma unroll
       for (int e = 0; e < 4; ++e) ra[r][e] = ok ? pa[e] : (T)0;
     }
-    if (bvalid) {
-      const int8_t *o = tb.il_off + (oc * 189 + k) * 3;
-      const int x = imod(bc[0] + o[0], bn), y = imod(bc[1] + o[1], bn), z = imod(bc[2] + o[2], bn);
+    const int8_t *o = tb.il_off + (oc * 189 + k) * 3;
+    const int bx = bc[0] + o[0], by = bc[1] + o[1], bz = bc[2] + o[2];
+    const bool inside = bx >= 0 && bx < bn && by >= 0 && by < bn && bz >= 0 && bz < bn;
+    if (bvalid && (inside || !ch.free_space)) {  // free space: no images
+      const int x = imod(bx, bn), y = imod(by, bn), z = imod(bz, bn);
       const double *pb = bsrc + (size_t)lin3(bn, x, y, z) * Cs + s0 + brow;
 #pragma unroll
       for (int e = 0; e < 4; ++e) rb[e] = (T)pb[e];
@@ -378,6 +380,7 @@ __global__ void __launch_bounds__(WG_SETUP) k_p2l_direct(const Chain *chains, Ta
     const int k = (int)(it >> (3 * sh)), j = (int)(it & ((1LL << (3 * sh)) - 1));
     const int8_t *o = tb.il_off + (oc * 189 + k) * 3;
     const int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
+    if (ch.free_space && (b[0] < 0 || b[0] >= n || b[1] < 0 || b[1] >= n || b[2] < 0 || b[2] >= n)) continue;
     int leaf[3];
     double shift[3];
     for (int d = 0; d < 3; ++d) {
@@ -505,7 +508,7 @@ __global__ void __launch_bounds__(WG_SETUP) k_energy(const Chain *chains, Tabs t
       int s = lin3(n, imod(b[0], n), imod(b[1], n), imod(b[2], n));
       double sh[3] = {ifloordiv(b[0], n) * a, ifloordiv(b[1], n) * a, ifloordiv(b[2], n) * a};
       bool zero = ifloordiv(b[0], n) == 0 && ifloordiv(b[1], n) == 0 && ifloordiv(b[2], n) == 0;
-      int cnt = ch.bin_cnt[s];
+      int cnt = (ch.free_space && !zero) ? 0 : ch.bin_cnt[s];  // free space: no images
       for (int j = 0; j < cnt; ++j) {
         if (zero && ch.bin_id[(size_t)s * ch.B + j] == i) continue;
         double4 pj = ch.bin_p[(size_t)s * ch.B + j];
@@ -533,12 +536,14 @@ __global__ void k_energy_final(const Chain *chains, Tabs tb, int mode) {
   const int nb = (ch.N + NG - 1) / NG;
   double u = 0.0;
   for (int b = 0; b < nb; ++b) u += ch.red[b];
-  double eh = 0.0;
-  for (int s = 0; s < tb.C; ++s) eh += tb.wdot[s] * ch.K[s] * ch.H[s];
-  const double a = ch.a;
-  u += 0.5 * eh / a;
-  const double d2 = ch.dip[0] * ch.dip[0] + ch.dip[1] * ch.dip[1] + ch.dip[2] * ch.dip[2];
-  u += -2.0 * M_PI / (3.0 * a * a * a) * d2;
+  if (!ch.free_space) {  // far lattice and tin-foil terms (Sec. 3.4)
+    double eh = 0.0;
+    for (int s = 0; s < tb.C; ++s) eh += tb.wdot[s] * ch.K[s] * ch.H[s];
+    const double a = ch.a;
+    u += 0.5 * eh / a;
+    const double d2 = ch.dip[0] * ch.dip[0] + ch.dip[1] * ch.dip[1] + ch.dip[2] * ch.dip[2];
+    u += -2.0 * M_PI / (3.0 * a * a * a) * d2;
+  }
   ch.scratch[8] = u;
   if (mode >= 1) ch.U[0] = u;
   if (mode >= 2) ch.U[1] = u;
