@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
 # they were taken on; otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "5a612eb1dad2bf6e00a5ffcf23060a6f8e6830eb081e07fd121b0427daea1789",
+    "src_sha256": "a984d15c6b64f81f742615ba77527782ca6ab403205911384e19b36336cbd7a3",
     "steps": 200000, "warmup": 2000,
-    "fetch_kib": 63126343.25, "fetch_scale": 2.0,
-    "write_kib": 91758462.6875, "write_scale": 1.0,
+    "fetch_kib": 76579090.25, "fetch_scale": 2.0,
+    "write_kib": 91758462.625, "write_scale": 1.0,
 }
 
 
