@@ -580,7 +580,12 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
 // split over NG/8 groups (partial sums added in a fixed order); level 3: 64
 // stored cells over the groups; levels >= 4: the items of both interaction
 // lists over the groups.
-template <int GS, int PM, typename R, int NT>
+//
+// With PIPE (the batched kernel) each group requests the target of its next
+// fine item before it forms the current one (no two items share a target,
+// so the early read sees the value before this move); the results are the
+// same bit for bit.
+template <int GS, int PM, typename R, int NT, bool PIPE = false>
 __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
@@ -645,15 +650,25 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
   }
   // ---- levels >= 4: each item's target is loaded while its harmonics are formed
   const int nfine = L >= 4 ? (L - 3) * 378 : 0;
-  for (int i = g; i < nfine; i += NG) {
-    FineItem it = fine_item(ch, tb, sm.il_off, mv, 4 + i / 378, i % 378);
-    if (!it.active) continue;
-    double old[NJ];
+  FineItem nx;
+  double nold[NJ];
+  auto fetch = [&](int ii) {
+    nx = fine_item(ch, tb, sm.il_off, mv, 4 + ii / 378, ii % 378);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       int k = lane + j * GS;
-      old[j] = k < C ? glb(it.dst)[k] : 0.0;
+      nold[j] = nx.active && k < C ? glb(nx.dst)[k] : 0.0;
     }
+  };
+  if (PIPE && g < nfine) fetch(g);
+  for (int i = g; i < nfine; i += NG) {
+    if (!PIPE) fetch(i);
+    const FineItem it = nx;
+    double old[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) old[j] = nold[j];
+    if (PIPE && i + NG < nfine) fetch(i + NG);
+    if (!it.active) continue;
     group_harmonics<GS, PM, 2, false, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
                                          (R)it.q0, buf);
     if (it.two) {

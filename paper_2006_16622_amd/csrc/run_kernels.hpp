@@ -92,8 +92,11 @@ __device__ __forceinline__ void move_from_draw(const RunParams &rp, const Chain 
   }
 }
 
+// one workgroup per CU is the shape of the batched launch (256 chains), so
+// a workgroup may use the whole register file (2 wavefronts per SIMD)
 template <int GS, int PM, typename R, bool MP = false>
-__global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
+__global__ void __launch_bounds__(WG_BATCH) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
   constexpr int NT = WG_BATCH;
   constexpr int NG = NT / GS;
   extern __shared__ double lds[];
@@ -164,7 +167,7 @@ __global__ void __launch_bounds__(WG_BATCH) k_run_batched(const Chain *chains, T
       if constexpr (MP)
         accept_mp_wg<GS, PM, NT>(ch, tb, mv, sm.rec);
       else
-        accept_all_wg<GS, PM, R>(ch, tb, mv, sm);
+        accept_all_wg<GS, PM, R, NT, true>(ch, tb, mv, sm);
       int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, po.dE, sm);
       if (t == 0) {
         nacc += 1;
