@@ -75,3 +75,15 @@ def test_full_lattice_sum_z4():
     ref = _extrapolate(_shell_partial_sums(56, 4, 0), 56) + near
     assert full == pytest.approx(ref, abs=1e-10)
     assert full == pytest.approx(3.1082266827, abs=1e-9)
+
+
+@pytest.mark.parametrize("l,m", [(16, 0), (16, 4), (24, 0), (24, 8), (32, 4), (40, 0), (48, 0), (48, 12)])
+def test_high_degree_lattice_sums_to_absolute_precision(l, m):
+    # for l >= 16 the far sum converges absolutely and fast (the tail beyond
+    # cube shell K is O(K^(2-l))), so plain shell sums to K = 24 are exact to
+    # rounding; the Ewald-split evaluation keeps an absolute error of about
+    # 1e-15 at every degree, which is the floor of the highest sums (S_48 is
+    # about 4e-15)
+    S = O.lattice_sums(48)
+    ref = _shell_partial_sums(24, l, m)[-1]
+    assert abs(S[O.idx(l, m)].real - ref) < 1e-14
