@@ -113,14 +113,23 @@ struct ProposeOut {
 // is run by the last wavefront at the start, `spare` by the last wavefront
 // while the others evaluate the expansions. With LOCAL false the first sum
 // (the local expansions) is left out: the multipole-based variant adds its
-// own far field.
+// own far field. When gate.active() holds, the local expansions may still be
+// being updated by other workgroups: everything that does not read them (the
+// near field, the two lattice points and the quadratic lattice term) is
+// formed first, then every thread calls gate(), which returns once the
+// expansions are current, and only then are they read.
 struct NoWork {
   __device__ void operator()(int) const {}
 };
+struct NoGate {
+  __device__ bool active() const { return false; }
+  __device__ void operator()() const {}
+};
 
-template <int GS, int PM, typename R, bool LOCAL = true, int NT, typename Spare, typename Early = NoWork>
-__device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm,
-                                 Spare &&spare, Early &&early = NoWork{}) {
+template <int GS, int PM, typename R, bool LOCAL = true, int NT, typename Spare, typename Early = NoWork,
+          typename Gate = NoGate>
+__device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm,
+                                 Spare &&spare, Early &&early = NoWork{}, Gate &&gate = NoGate{}) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   const int Cs = tb.Cs, C = tb.C;
@@ -130,13 +139,14 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
   const int L = ch.L, d = ch.d, B = ch.B;
   const int npts = LOCAL ? 2 * d + 2 : 2;
   const int nL = 1 << (L - 1);
+  const bool gated = gate.active();
 
   if (t >= NT - 64) early(t - (NT - 64));
 
   // ---- the first round of level coefficients is requested before the near
   // field, so that its memory latency overlaps the direct sum
   double lv0[NJ];
-  if (g >= 2 && g < npts) {
+  if (!gated && g >= 2 && g < npts) {
     const int l = 2 + (g - 2) / 2, side = (g - 2) % 2, n = 1 << (l - 1);
     const int *c = side ? mv.c1[l] : mv.c0[l];
     const auto src = glb(ch.Ld) + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
@@ -147,7 +157,9 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     }
   }
 
-  // ---- near field: 4 threads per near cell, first slot loaded with the count
+  // ---- near field: 4 threads per near cell, the first two slots of each
+  // thread loaded with the count (bins of up to 8 charges take one round of
+  // loads; the capacity is at least 32 slots)
   double dold = 0.0, dnew = 0.0;
   int singular = 0;
   if (t == 0) ints[I_MASK] = 0;
@@ -164,10 +176,15 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     const int cnt = (ch.free_space && w != 13) ? 0 : glb(ch.bin_cnt)[cell];  // free space: no images
     int id = glb(ch.bin_id)[base + j0];
     double4 pj = ld_rec(ch.bin_p, base + j0);
+    const int id1 = glb(ch.bin_id)[base + j0 + 4];
+    const double4 pj1 = ld_rec(ch.bin_p, base + j0 + 4);
     if (ee == 13 && j0 == 0) ints[side ? I_CNTNEW : I_CNTOLD] = cnt;
     const double *x = side ? mv.rn : mv.r;
     for (int j = j0; j < cnt; j += 4) {
-      if (j != j0) {
+      if (j == j0 + 4) {
+        id = id1;
+        pj = pj1;
+      } else if (j != j0) {
         id = glb(ch.bin_id)[base + j];
         pj = ld_rec(ch.bin_p, base + j);
       }
@@ -194,87 +211,157 @@ __device__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb, const Move &mv
     }
   }
 
-  // ---- local expansions at the 2d level points and the two lattice points
-  const bool spare_in_loop = npts <= NG - 64 / GS;  // the last wavefront has no point
-  for (int base = 0; base < npts; base += NG) {
-    int pt = base + g;
-    if (pt < npts) {
-      double *buf;
-      double x[3], hh;
-      const double *src;
-      if (pt < 2) {  // lattice: expansion about the box centre, scaled by a
-        buf = pt ? sm.latN : sm.latO;
-        const double *r = pt ? mv.rn : mv.r;
-        hh = a;
-        for (int k = 0; k < 3; ++k) x[k] = (r[k] - 0.5 * a) / a;
-        src = sm.H;
-      } else {
-        int l = 2 + (pt - 2) / 2, side = (pt - 2) % 2;
-        buf = sm.gbuf + (size_t)g * Cs;
-        int n = 1 << (l - 1);
-        hh = a / n;
-        const int *c = side ? mv.c1[l] : mv.c0[l];
-        const double *r = side ? mv.rn : mv.r;
-        for (int k = 0; k < 3; ++k) x[k] = (r[k] - (c[k] + 0.5) * hh) / hh;
-        src = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
-      }
-      // the expansion coefficients are loaded while the harmonics are formed
-      double lv[NJ];
-      if (base == 0 && pt >= 2) {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) lv[j] = lv0[j];
-      } else if (pt < 2) {  // the lattice vector H, in LDS
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          int s = lane + j * GS;
-          lv[j] = s < C ? src[s] : 0.0;
-        }
-      } else {
-        const auto gsrc = glb(src);
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          int s = lane + j * GS;
-          lv[j] = s < C ? gsrc[s] : 0.0;
-        }
-      }
-      if (pt < 2)  // the periodic lattice term stays in FP64
-        group_harmonics<GS, PM, 0, false>(lane, tb, sm.rec, x[0], x[1], x[2], 1.0, buf);
-      else
-        group_harmonics<GS, PM, 0, false, R>(lane, tb, sm.template rec_of<R>(), (R)x[0], (R)x[1], (R)x[2],
-                                             R(1), buf);
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      double acc = 0.0;
+  // ---- one expansion point per group: the local expansion of level
+  // l = 2 + (pt - 2) / 2 about the old (even pt) or new (odd pt) cell, or
+  // for pt < 2 the lattice expansion about the box centre, scaled by a.
+  // geom: the point in cell units, the cell size, the group's harmonics
+  // buffer and the coefficients; harm: the harmonics of the point into the
+  // buffer; dot: the expansion's value from the coefficients and the buffer.
+  auto geom = [&](int pt, double x[3], double &hh, double *&buf, const double *&src) __attribute__((always_inline)) {
+    if (pt < 2) {
+      buf = pt ? sm.latN : sm.latO;
+      const double *r = pt ? mv.rn : mv.r;
+      hh = a;
+      for (int k = 0; k < 3; ++k) x[k] = (r[k] - 0.5 * a) / a;
+      src = sm.H;
+    } else {
+      int l = 2 + (pt - 2) / 2, side = (pt - 2) % 2;
+      buf = sm.gbuf + (size_t)g * Cs;
+      int n = 1 << (l - 1);
+      hh = a / n;
+      const int *c = side ? mv.c1[l] : mv.c0[l];
+      const double *r = side ? mv.rn : mv.r;
+      for (int k = 0; k < 3; ++k) x[k] = (r[k] - (c[k] + 0.5) * hh) / hh;
+      src = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
+    }
+  };
+  auto load = [&](int pt, const double *src, double lv[NJ]) __attribute__((always_inline)) {
+    if (pt < 2) {  // the lattice vector H, in LDS
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         int s = lane + j * GS;
-        if (s < C) acc += lv[j] * sm.wl2p[s] * buf[s];
+        lv[j] = s < C ? src[s] : 0.0;
       }
-      acc = group_sum<GS>(acc);
-      if (lane == 0) sm.vals[pt] = acc / hh;
-    } else if (base == 0 && spare_in_loop && t >= NT - 64) {
+    } else {
+      const auto gsrc = glb(src);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        int s = lane + j * GS;
+        lv[j] = s < C ? gsrc[s] : 0.0;
+      }
+    }
+  };
+  auto harm = [&](int pt, const double x[3], double *buf) __attribute__((always_inline)) {
+    if (pt < 2)  // the periodic lattice term stays in FP64
+      group_harmonics<GS, PM, 0, false>(lane, tb, sm.rec, x[0], x[1], x[2], 1.0, buf);
+    else
+      group_harmonics<GS, PM, 0, false, R>(lane, tb, sm.template rec_of<R>(), (R)x[0], (R)x[1], (R)x[2],
+                                           R(1), buf);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  };
+  auto dot = [&](int pt, const double lv[NJ], const double *buf, double hh) __attribute__((always_inline)) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      int s = lane + j * GS;
+      if (s < C) acc += lv[j] * sm.wl2p[s] * buf[s];
+    }
+    acc = group_sum<GS>(acc);
+    if (lane == 0) sm.vals[pt] = acc / hh;
+  };
+  // the whole point; the coefficients are loaded while the harmonics are formed
+  auto point = [&](int pt, bool preloaded) __attribute__((always_inline)) {
+    double x[3], hh, *buf;
+    const double *src;
+    geom(pt, x, hh, buf, src);
+    double lv[NJ];
+    if (preloaded) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) lv[j] = lv0[j];
+    } else {
+      load(pt, src, lv);
+    }
+    harm(pt, x, buf);
+    dot(pt, lv, buf, hh);
+  };
+
+  // ---- far lattice quadratic term: dk = q (conj T(r') - conj T(r)), 1/2 dk.R(dk)
+  // (this thread's share; needs both lattice points)
+  auto lattice_quad = [&]() __attribute__((always_inline)) {
+    for (int s = t; s < C; s += NT) sm.dk[s] = q * sm.sgnc[s] * (sm.latN[s] - sm.latO[s]);
+    __syncthreads();
+    double v = 0.0;
+    lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk,
+                     [&](int s, double y) { v += sm.wdot[s] * sm.dk[s] * y; });
+    return v;
+  };
+  // self-interaction with the old position's images (Sec. 3.4)
+  auto self_term = [&]() __attribute__((always_inline)) {
+    double self = 0.0;
+    if (t < 27 && !((ints[I_MASK] >> t) & 1) && (!ch.free_space || t == 13)) {
+      double sx = (t % 3 - 1) * a, sy = ((t / 3) % 3 - 1) * a, sz = (t / 9 - 1) * a;
+      double dx = mv.rn[0] - (mv.r[0] + sx), dy = mv.rn[1] - (mv.r[1] + sy), dz = mv.rn[2] - (mv.r[2] + sz);
+      self = q * q / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    return self;
+  };
+
+  // ---- the expansion points, NG at a time; the last wavefront runs `spare`
+  // in the first round when it holds no point
+  const bool spare_in_loop = npts <= NG - 64 / GS;
+  double part[4];
+  int sing;
+  if (gated && npts <= NG) {
+    // before the gate: the harmonics of every point, the lattice values,
+    // the next draw, the quadratic lattice term and the partial sums
+    double x[3], hh, *buf;
+    const double *src;
+    if (g < npts) {
+      geom(g, x, hh, buf, src);
+      harm(g, x, buf);
+      if (g < 2) {
+        double lv[NJ];
+        load(g, src, lv);
+        dot(g, lv, buf, hh);
+      }
+    } else if (spare_in_loop && t >= NT - 64) {
       spare(t - (NT - 64));
     }
     __syncthreads();
+    if (!spare_in_loop && t >= NT - 64) spare(t - (NT - 64));
+    part[0] = dold;
+    part[1] = dnew;
+    part[3] = lattice_quad();
+    part[2] = self_term();
+    wg_sum4<NT>(part, sm.red);
+    sing = __syncthreads_or(singular);
+    gate();
+    // after it: only the loads of the local expansions and their products
+    if (g >= 2 && g < npts) {
+      double lv[NJ];
+      load(g, src, lv);
+      dot(g, lv, buf, hh);
+    }
+    __syncthreads();
+  } else {
+    if (gated) gate();  // several rounds of points: no overlap
+    for (int base = 0; base < npts; base += NG) {
+      int pt = base + g;
+      if (pt < npts)
+        point(pt, !gated && base == 0 && pt >= 2);
+      else if (base == 0 && spare_in_loop && t >= NT - 64)
+        spare(t - (NT - 64));
+      __syncthreads();
+    }
+    if (!spare_in_loop && t >= NT - 64) spare(t - (NT - 64));
+    part[0] = dold;
+    part[1] = dnew;
+    part[3] = lattice_quad();
+    part[2] = self_term();
+    wg_sum4<NT>(part, sm.red);
+    sing = __syncthreads_or(singular);
   }
-  if (!spare_in_loop && t >= NT - 64) spare(t - (NT - 64));
-
-  // ---- far lattice quadratic term: dk = q (conj T(r') - conj T(r)), 1/2 dk.R(dk)
-  for (int s = t; s < C; s += NT) sm.dk[s] = q * sm.sgnc[s] * (sm.latN[s] - sm.latO[s]);
-  __syncthreads();
-  // self-interaction with the old position's images (Sec. 3.4)
-  double self = 0.0;
-  if (t < 27 && !((ints[I_MASK] >> t) & 1) && (!ch.free_space || t == 13)) {
-    double sx = (t % 3 - 1) * a, sy = ((t / 3) % 3 - 1) * a, sz = (t / 9 - 1) * a;
-    double dx = mv.rn[0] - (mv.r[0] + sx), dy = mv.rn[1] - (mv.r[1] + sy), dz = mv.rn[2] - (mv.r[2] + sz);
-    self = q * q / sqrt(dx * dx + dy * dy + dz * dz);
-  }
-  double quad = 0.0;
-  lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk,
-               [&](int s, double v) { quad += sm.wdot[s] * sm.dk[s] * v; });
-  double part[4] = {dold, dnew, self, quad};
-  wg_sum4<NT>(part, sm.red);
-  int sing = __syncthreads_or(singular);
 
   ProposeOut out;
   double dE = 0.0;
@@ -434,7 +521,7 @@ __device__ __forceinline__ void coarse_contrib(const Tabs &tb, const R *rec, con
 // in out[0..C), for dst[0]. The arithmetic and its order are those of an
 // immediate update. Returns whether the block is coarse.
 template <int GS, int PM, typename R, int NT>
-__device__ bool accept_block_compute(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS, NT> &sm,
+__device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs &tb, const Move &mv, int blk, Lds<GS, NT> &sm,
                                      double *out, double **dst) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
@@ -586,7 +673,7 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
 // so the early read sees the value before this move); the results are the
 // same bit for bit.
 template <int GS, int PM, typename R, int NT, bool PIPE = false>
-__device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm) {
+__device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
   constexpr int SPLIT2 = NG / 8;  // NG is 16 or 8
@@ -694,7 +781,7 @@ __device__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, L
 // bin records kept in LDS (I_SLOTK, I_CNTOLD, I_CNTNEW, I_IDLAST, stash[0]).
 // Returns nonzero on bin overflow.
 template <int GS, int PM, int NT>
-__device__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &mv, double dE, Lds<GS, NT> &sm) {
+__device__ __forceinline__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &mv, double dE, Lds<GS, NT> &sm) {
   const int C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
   int *ints = sm.ints;

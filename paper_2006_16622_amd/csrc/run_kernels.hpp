@@ -253,6 +253,55 @@ __host__ __device__ inline size_t spec_extra_bytes(int k, int NG, int Cs) {
   return (size_t)(k - 1) * NG * Cs * sizeof(double) + (size_t)k * NG * sizeof(double *);
 }
 
+// post move `num` in its mailbox slot (one thread)
+__device__ __forceinline__ void post_move(double *mb, unsigned *mvseq, unsigned num, const Move &mv) {
+  const auto slot = glb(mb) + 8 * (num & 1);
+  slot[0] = (double)mv.idx;
+  slot[1] = mv.q;
+  for (int k = 0; k < 3; ++k) {
+    slot[2 + k] = mv.r[k];
+    slot[5 + k] = mv.rn[k];
+  }
+  st_release(mvseq, num);
+}
+
+// the whole workgroup: wavefront 0 waits until every helper has finished
+// move `target`, then every thread acquires their rows; false on time-out
+// (flag: LDS word, 0 or 1)
+__device__ __forceinline__ bool wait_helpers(unsigned *doneflag, int G, unsigned target, int *flag) {
+  if (threadIdx.x < 64) {
+    bool ok = spin_all_equal(doneflag, G, target, SPIN_LIMIT);
+    if (threadIdx.x == 0) *flag = ok ? 0 : 1;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const bool ok = *flag == 0;
+  __syncthreads();
+  return ok;
+}
+
+// gate of a proposal that follows an accepted move (active when `on`):
+// wait for the helpers' rows of move num - 1, then the last wavefront posts
+// move num; a helper never sees a move before it has stored the accepted one
+// before it. ticks: LDS, the time of the wait (thread 0).
+struct HelperGate {
+  bool on;
+  int G;
+  unsigned num;
+  unsigned *doneflag, *mvseq;
+  double *mb;
+  const Move *mv;
+  int *flag;
+  uint64_t *ticks;
+  __device__ bool active() const { return on; }
+  __device__ void operator()() const {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    const bool ok = wait_helpers(doneflag, G, num - 1, flag);
+    if (threadIdx.x == 0) *ticks = __builtin_amdgcn_s_memrealtime() - t0;
+    if (ok && threadIdx.x == WG_SINGLE - 64) post_move(mb, mvseq, num, *mv);
+  }
+};
+
 // Protocol of the whole-GPU chain (sync words of the workspace):
 //   sync[0] mvseq   number of the latest posted move (1, 2, ... per launch)
 //   sync[1] dec     2 * number + accepted, once that move is decided
@@ -278,6 +327,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   __shared__ int s_flag, s_acc;
   __shared__ unsigned s_seq;
   __shared__ double s_u;
+  __shared__ uint64_t s_ticks;
   __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
   const int t = threadIdx.x, w = blockIdx.x, G = gridDim.x;
   if (t == 0) chl = ch_arg;
@@ -302,6 +352,9 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     double prev_rn[3] = {0, 0, 0};
     const int64_t s0 = rp.first ? rp.first[0] : 0;
     int64_t acc_launch = 0;
+    // the rows of the last accepted move may still be in flight (helpers
+    // finish them while the next proposal forms its other terms)
+    bool pending = false;
     if (t == 0 && s0 < rp.steps) draw_into(rp, c, s0, ch, D, nd);
     __syncthreads();
     for (int64_t step = s0; step < rp.steps; ++step) {
@@ -317,26 +370,30 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       const double u = s_u;
       // the last wavefront of the proposal posts the move to the helpers
       // first (its release fence is hidden behind the near field and the
-      // expansion evaluations) and later fetches the next draw
+      // expansion evaluations) and later fetches the next draw. After an
+      // accept the post waits for the gate: a helper must not see this move
+      // before it has stored the accepted one.
+      HelperGate gate{pending, G, num, doneflag, mvseq, mb, &mv, &s_flag, &s_ticks};
       ProposeOut po = propose_wg<GS, PM, R>(
           ch, tb, mv, sm,
           [&](int lane) {
             if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
           },
           [&](int lane) {
-            if (lane == 0 && G > 1) {
-              const auto slot = glb(mb) + 8 * (num & 1);
-              slot[0] = (double)mv.idx;
-              slot[1] = mv.q;
-              for (int k = 0; k < 3; ++k) {
-                slot[2 + k] = mv.r[k];
-                slot[5 + k] = mv.rn[k];
-              }
-              st_release(mvseq, num);
-            }
-          });
+            if (lane == 0 && G > 1 && !pending) post_move(mb, mvseq, num, mv);
+          },
+          gate);
       uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
-      tick_prop += t_1 - t_0;
+      const uint64_t gate_ticks = pending ? s_ticks : 0;
+      tick_prop += t_1 - t_0 - gate_ticks;
+      tick_wait += gate_ticks;
+      if (pending) {
+        pending = false;
+        if (s_flag) {  // a helper did not finish the last accepted move
+          status = -8;
+          break;
+        }
+      }
       if (t == 0) {
         int acc = !po.singular && (u < exp(-rp.beta * po.dE));
         s_acc = acc;
@@ -366,27 +423,22 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
           nacc += 1;
           dEsum += po.dE;
         }
-        uint64_t t_2 = __builtin_amdgcn_s_memrealtime();
-        tick_acc += t_2 - t_1;
-        if (G > 1) {
-          if (t < 64) {
-            bool ok = spin_all_equal(doneflag, G, num, SPIN_LIMIT);
-            if (t == 0) s_flag = ok ? 0 : 1;
-          }
-          __syncthreads();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          if (s_flag) {
-            status = -8;
-            break;
-          }
-        }
-        tick_wait += __builtin_amdgcn_s_memrealtime() - t_2;
+        tick_acc += __builtin_amdgcn_s_memrealtime() - t_1;
+        // the next proposal waits for the helpers (gate) only where it
+        // reads the expansions
+        pending = G > 1;
         if (ovf) {
           status = -7;
           break;
         }
         if (rp.acc_limit && ++acc_launch >= rp.acc_limit) break;
       }
+    }
+    // a helper must have stored the last accepted move before it is stopped
+    if (pending) {
+      uint64_t t_2 = __builtin_amdgcn_s_memrealtime();
+      if (!wait_helpers(doneflag, G, num, &s_flag) && status == 0) status = -8;
+      tick_wait += __builtin_amdgcn_s_memrealtime() - t_2;
     }
     if (G > 1 && t == 0) {
       st_release(stop, 1u);
