@@ -219,6 +219,16 @@ __device__ __forceinline__ bool spin_until_ne(unsigned *p, unsigned old, unsigne
     __builtin_amdgcn_s_sleep(1);
   }
 }
+// bounded spin until the counter *p has reached `target` (counters of one
+// launch stay far below 2^31, so the signed difference orders them)
+__device__ __forceinline__ bool spin_until_reached(unsigned *p, unsigned target, uint64_t limit) {
+  uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  while (true) {
+    if ((int)(ld_relaxed(p) - target) >= 0) return true;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
 // the same wait by a whole wavefront: the value is made uniform, so every
 // lane takes the same exit
 __device__ __forceinline__ bool wave_spin_until_ne(unsigned *p, unsigned old, unsigned &val, uint64_t limit) {
@@ -281,42 +291,43 @@ __device__ __forceinline__ bool wait_helpers(unsigned *doneflag, int G, unsigned
 }
 
 // gate of a proposal that follows an accepted move (active when `on`):
-// wait for the helpers' rows of move num - 1, then the last wavefront posts
-// move num; a helper never sees a move before it has stored the accepted one
-// before it. ticks: LDS, the time of the wait (thread 0).
+// wait for the helpers' rows of move num - 1. ticks: LDS, the time of the
+// wait (thread 0).
 struct HelperGate {
   bool on;
   int G;
   unsigned num;
-  unsigned *doneflag, *mvseq;
-  double *mb;
-  const Move *mv;
+  unsigned *doneflag;
   int *flag;
   uint64_t *ticks;
   __device__ bool active() const { return on; }
   __device__ void operator()() const {
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    const bool ok = wait_helpers(doneflag, G, num - 1, flag);
+    wait_helpers(doneflag, G, num - 1, flag);
     if (threadIdx.x == 0) *ticks = __builtin_amdgcn_s_memrealtime() - t0;
-    if (ok && threadIdx.x == WG_SINGLE - 64) post_move(mb, mvseq, num, *mv);
   }
 };
 
 // Protocol of the whole-GPU chain (sync words of the workspace):
 //   sync[0] mvseq   number of the latest posted move (1, 2, ... per launch)
 //   sync[1] dec     2 * number + accepted, once that move is decided
-//   sync[2] stop, sync[3] error, sync[64 + w] done flag of helper w
+//   sync[2] stop, sync[3] error, sync[64 + w] done flag of helper w (the
+//                   number of the last accepted move whose rows it stored)
 //   mailbox         two slots of 8 doubles (idx, q, r, r'), slot = number & 1
-// Workgroup 0 posts each move early in its proposal. While it proposes, every
-// helper reads the move (validated like a seqlock: a slot is only rewritten
-// two moves later), locates it and forms, in LDS, the updated rows of its
-// accept blocks without writing them (speculation). When the decision says
-// accepted, the helpers store those rows and raise their done flags;
-// workgroup 0 does its bookkeeping meanwhile and waits for all flags before
-// the next proposal reads any expansion. A rejected move's rows are
-// dropped. A helper never misses an accepted move: workgroup 0 posts the
-// next move only after every helper has finished it. Every wait is
-// bounded; on time-out the chain stops with an error status.
+// Workgroup 0 posts each move at the start of its proposal. Every helper
+// takes the moves in order; for each it reads the move, locates it and
+// forms, in LDS, the updated rows of its accept blocks without writing them
+// (speculation), then waits for the decision. If accepted, it stores those
+// rows and raises its done flag; else they are dropped. Workgroup 0 does its
+// bookkeeping meanwhile; its next proposal forms every term that does not
+// read a local expansion and then waits for all done flags (the gate).
+// Hence the decision of a move m is published only after every helper has
+// stored the accepted move before it: a helper that finds the decision word
+// already past m knows m was rejected, and a mailbox slot, rewritten two
+// moves later, can only have changed under a helper still reading a
+// rejected move (whose rows are dropped). A helper that finds a move
+// already decided rejected skips it. Every wait is bounded; on time-out the
+// chain stops with an error status.
 template <int GS, int PM, typename R>
 __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb, RunParams rp) {
   constexpr int NT = WG_SINGLE;
@@ -370,17 +381,15 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       const double u = s_u;
       // the last wavefront of the proposal posts the move to the helpers
       // first (its release fence is hidden behind the near field and the
-      // expansion evaluations) and later fetches the next draw. After an
-      // accept the post waits for the gate: a helper must not see this move
-      // before it has stored the accepted one.
-      HelperGate gate{pending, G, num, doneflag, mvseq, mb, &mv, &s_flag, &s_ticks};
+      // expansion evaluations) and later fetches the next draw
+      HelperGate gate{pending, G, num, doneflag, &s_flag, &s_ticks};
       ProposeOut po = propose_wg<GS, PM, R>(
           ch, tb, mv, sm,
           [&](int lane) {
             if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
           },
           [&](int lane) {
-            if (lane == 0 && G > 1 && !pending) post_move(mb, mvseq, num, mv);
+            if (lane == 0 && G > 1) post_move(mb, mvseq, num, mv);
           },
           gate);
       uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
@@ -466,23 +475,27 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   double **sdst = (double **)(xbuf + (size_t)(kmax - 1) * NG * tb.Cs);
   auto spec = [&](int k) { return k == 0 ? sm.gbuf : xbuf + (size_t)(k - 1) * NG * tb.Cs; };
   __shared__ bool s_coarse[SPEC_MAX];
-  unsigned cur = 0;  // latest move number seen
+  __shared__ int s_skip;
+  unsigned cur = 0;  // number of the last move taken
   while (true) {
-    // a move newer than `cur`
+    const unsigned num = cur + 1;
+    // wait until move `num` is posted; the stop flag is stored before the
+    // number that follows the last move
     if (t == 0) {
-      unsigned v;
-      bool ok = spin_until_ne(mvseq, cur, v, SPIN_LIMIT);
+      bool ok = spin_until_reached(mvseq, num, SPIN_LIMIT);
       s_flag = ok ? 0 : 1;
       if (ok) {
-        s_seq = v;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the stop flag is stored before the number
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (__hip_atomic_load(glb(stop), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) s_flag = 2;
+        // a move already decided rejected (its decision, or a later one, is out) is skipped
+        const unsigned d = ld_relaxed(dec);
+        s_skip = (d >> 1) > num || ((d >> 1) == num && !(d & 1u));
       }
     }
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int f = s_flag;
-    const unsigned num = s_seq;
+    const bool skip = s_skip;
     __syncthreads();
     if (f == 1) {
       if (t == 0) st_relaxed(err, 1u);
@@ -490,10 +503,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     }
     if (f == 2) return;
     cur = num;
-    // read the move. Its slot is rewritten two moves later; a helper can
-    // still be reading it then only if this move and the next were both
-    // rejected (an accepted move holds workgroup 0 until every helper has
-    // finished it), so a mixed read only ever feeds rows that are dropped.
+    if (skip) continue;
     if (t == 0) {
       const auto slot = glb(mb) + 8 * (num & 1);
       double m[8];
@@ -515,17 +525,23 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       if (t == 0) s_coarse[k] = coarse;
       __syncthreads();
     }
-    // the decision of this move (or a newer move, which means rejected)
+    // the decision of this move (a later one means rejected). A move never
+    // decided (workgroup 0 stopped on an error) ends the wait at the stop
+    // flag: an accepted move is stored by every helper before the stop.
     if (t == 0) {
       uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-      int res = 0;  // 0 rejected, 1 accepted, 2 time-out
+      int res = 0;  // 0 rejected, 1 accepted, 2 time-out, 3 stopped
       while (true) {
         const unsigned d = ld_relaxed(dec);
         if ((d >> 1) == num) {
           res = (int)(d & 1u);
           break;
         }
-        if ((d >> 1) > num || ld_relaxed(mvseq) != num) break;
+        if ((d >> 1) > num) break;
+        if (ld_relaxed(stop)) {
+          res = 3;
+          break;
+        }
         if (__builtin_amdgcn_s_memrealtime() - t0 > SPIN_LIMIT) {
           res = 2;
           break;
@@ -542,6 +558,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       if (t == 0) st_relaxed(err, 1u);
       return;
     }
+    if (res == 3) return;
     if (res == 1) {
       for (int k = 0, b = w - 1; b < nblk; ++k, b += G - 1)
         accept_block_store<GS, NT>(tb, s_coarse[k], spec(k), sdst + (size_t)k * NG);
