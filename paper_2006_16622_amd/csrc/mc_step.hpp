@@ -143,8 +143,9 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
 
   if (t >= NT - 64) early(t - (NT - 64));
 
-  // ---- the first round of level coefficients is requested before the near
-  // field, so that its memory latency overlaps the direct sum
+  // ---- the level coefficients of the points are requested first (one
+  // point per group), so that their memory latency overlaps the rest
+  const bool one_round = npts <= NG;
   double lv0[NJ];
   if (!gated && g >= 2 && g < npts) {
     const int l = 2 + (g - 2) / 2, side = (g - 2) % 2, n = 1 << (l - 1);
@@ -157,27 +158,40 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
     }
   }
 
-  // ---- near field: 4 threads per near cell, the first two slots of each
-  // thread loaded with the count (bins of up to 8 charges take one round of
-  // loads; the capacity is at least 32 slots)
+  // ---- near field: 4 threads per near cell. The count and the first two
+  // slots of each thread are requested here (bins of up to 8 charges take
+  // one round of loads; the capacity is at least 32 slots) and used later.
   double dold = 0.0, dnew = 0.0;
   int singular = 0;
   if (t == 0) ints[I_MASK] = 0;
+  const int e = t >> 2, j0 = t & 3;
+  const int side = e / 27, ee = e % 27;
+  int w = 13, cnt = 0, id = -1, id1 = -1;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  size_t base = 0;
+  double4 pj = make_double4(0.0, 0.0, 0.0, 0.0), pj1 = pj;
   if (t < 216) {
-    const int e = t >> 2, j0 = t & 3;
-    const int side = e / 27, ee = e % 27;
     const int *c = side ? mv.c1[L] : mv.c0[L];
     int b[3] = {c[0] + ee % 3 - 1, c[1] + (ee / 3) % 3 - 1, c[2] + ee / 9 - 1};
     const int cell = lin3(nL, imod(b[0], nL), imod(b[1], nL), imod(b[2], nL));
     const int fx = ifloordiv(b[0], nL), fy = ifloordiv(b[1], nL), fz = ifloordiv(b[2], nL);
-    const int w = (fx + 1) + 3 * (fy + 1) + 9 * (fz + 1);
-    const double sx = fx * a, sy = fy * a, sz = fz * a;
-    const size_t base = (size_t)cell * B;
-    const int cnt = (ch.free_space && w != 13) ? 0 : glb(ch.bin_cnt)[cell];  // free space: no images
-    int id = glb(ch.bin_id)[base + j0];
-    double4 pj = ld_rec(ch.bin_p, base + j0);
-    const int id1 = glb(ch.bin_id)[base + j0 + 4];
-    const double4 pj1 = ld_rec(ch.bin_p, base + j0 + 4);
+    w = (fx + 1) + 3 * (fy + 1) + 9 * (fz + 1);
+    sx = fx * a;
+    sy = fy * a;
+    sz = fz * a;
+    base = (size_t)cell * B;
+    cnt = (ch.free_space && w != 13) ? 0 : glb(ch.bin_cnt)[cell];  // free space: no images
+    id = glb(ch.bin_id)[base + j0];
+    pj = ld_rec(ch.bin_p, base + j0);
+    id1 = glb(ch.bin_id)[base + j0 + 4];
+    pj1 = ld_rec(ch.bin_p, base + j0 + 4);
+  }
+  // the loads stay in flight across the lattice term in the whole-GPU
+  // chain's workgroups; in the wider batched workgroup the registers this
+  // holds would spill
+  constexpr bool overlap = NT == WG_SINGLE;
+  auto near_sum = [&]() __attribute__((always_inline)) {
+    if (t >= 216) return;
     if (ee == 13 && j0 == 0) ints[side ? I_CNTNEW : I_CNTOLD] = cnt;
     const double *x = side ? mv.rn : mv.r;
     for (int j = j0; j < cnt; j += 4) {
@@ -209,7 +223,7 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
         v = pj.w / sqrt(r2);
       if (side) dnew += v; else dold += v;
     }
-  }
+  };
 
   // ---- one expansion point per group: the local expansion of level
   // l = 2 + (pt - 2) / 2 about the old (even pt) or new (odd pt) cell, or
@@ -307,45 +321,54 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
     return self;
   };
 
-  // ---- the expansion points, NG at a time; the last wavefront runs `spare`
-  // in the first round when it holds no point
-  const bool spare_in_loop = npts <= NG - 64 / GS;
+  const bool spare_in_loop = npts <= NG - 64 / GS;  // the last wavefront holds no point
   double part[4];
   int sing;
-  if (gated && npts <= NG) {
-    // before the gate: the harmonics of every point, the lattice values,
-    // the next draw, the quadratic lattice term and the partial sums
+  if (overlap && one_round) {
+    // while the near-field and coefficient loads are in flight: the two
+    // lattice points and the quadratic lattice term (LDS only)
     double x[3], hh, *buf;
     const double *src;
-    if (g < npts) {
+    if (g < 2) {
+      double lv[NJ];
+      geom(g, x, hh, buf, src);
+      load(g, src, lv);
+      harm(g, x, buf);
+      dot(g, lv, buf, hh);
+    }
+    __syncthreads();
+    part[3] = lattice_quad();
+    near_sum();
+    // the harmonics of the level points (and their values, when the
+    // coefficients are current); the last wavefront fetches the next draw
+    if (g >= 2 && g < npts) {
       geom(g, x, hh, buf, src);
       harm(g, x, buf);
-      if (g < 2) {
-        double lv[NJ];
-        load(g, src, lv);
-        dot(g, lv, buf, hh);
-      }
-    } else if (spare_in_loop && t >= NT - 64) {
+      if (!gated) dot(g, lv0, buf, hh);
+    } else if (g >= npts && spare_in_loop && t >= NT - 64) {
       spare(t - (NT - 64));
     }
     __syncthreads();
     if (!spare_in_loop && t >= NT - 64) spare(t - (NT - 64));
     part[0] = dold;
     part[1] = dnew;
-    part[3] = lattice_quad();
     part[2] = self_term();
     wg_sum4<NT>(part, sm.red);
     sing = __syncthreads_or(singular);
-    gate();
-    // after it: only the loads of the local expansions and their products
-    if (g >= 2 && g < npts) {
-      double lv[NJ];
-      load(g, src, lv);
-      dot(g, lv, buf, hh);
+    if (gated) {
+      // the local expansions are read only after the gate
+      gate();
+      if (g >= 2 && g < npts) {
+        double lv[NJ];
+        load(g, src, lv);
+        dot(g, lv, buf, hh);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   } else {
-    if (gated) gate();  // several rounds of points: no overlap
+    // the direct sum, then the points round by round (no overlap)
+    near_sum();
+    if (gated) gate();
     for (int base = 0; base < npts; base += NG) {
       int pt = base + g;
       if (pt < npts)

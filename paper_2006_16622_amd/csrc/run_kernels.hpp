@@ -254,6 +254,28 @@ __device__ __forceinline__ bool spin_all_equal(unsigned *flags, int G, unsigned 
   }
 }
 
+// a helper's wait before it reads target rows: wavefront 0 polls the done
+// flags of the helpers holding fine-level blocks (levels 4..L, bpl blocks
+// each; block b belongs to helper 1 + b % (G - 1)) of the levels in `lvmask`
+// until all have reached `target` (a flag may already be past it)
+__device__ __forceinline__ bool spin_level_helpers(unsigned *flags, int G, unsigned lvmask, int bpl,
+                                                   unsigned target, uint64_t limit) {
+  const int lane = threadIdx.x & 63;
+  uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  while (true) {
+    bool mine = true;
+    for (int l = 4; l < 32; ++l) {
+      if (!((lvmask >> l) & 1u)) continue;
+      const int b0 = 72 + (l - 4) * bpl;
+      for (int b = b0 + lane; b < b0 + bpl; b += 64)
+        mine = mine && ((int)(ld_relaxed(&flags[1 + b % (G - 1)]) - target) >= 0);
+    }
+    if (__all(mine)) return true;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 constexpr uint64_t SPIN_LIMIT = 100000000ull * 20;  // 20 s of the 100 MHz clock
 constexpr int SPEC_MAX = 8;  // accept blocks one helper of the whole-GPU run can hold
 
@@ -318,9 +340,13 @@ struct HelperGate {
 // takes the moves in order; for each it reads the move, locates it and
 // forms, in LDS, the updated rows of its accept blocks without writing them
 // (speculation), then waits for the decision. If accepted, it stores those
-// rows and raises its done flag; else they are dropped. Workgroup 0 does its
-// bookkeeping meanwhile; its next proposal forms every term that does not
-// read a local expansion and then waits for all done flags (the gate).
+// rows and raises its done flag; else they are dropped. A fine-level target
+// row may belong to another helper on the next move, so before a
+// speculation reads any row the helper waits until the done flags of the
+// helpers holding blocks of its fine levels have reached the last accepted
+// move. Workgroup 0 does its bookkeeping meanwhile; its next
+// proposal forms every term that does not read a local expansion and then
+// waits for all done flags (the gate).
 // Hence the decision of a move m is published only after every helper has
 // stored the accepted move before it: a helper that finds the decision word
 // already past m knows m was rejected, and a mailbox slot, rewritten two
@@ -476,7 +502,16 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   auto spec = [&](int k) { return k == 0 ? sm.gbuf : xbuf + (size_t)(k - 1) * NG * tb.Cs; };
   __shared__ bool s_coarse[SPEC_MAX];
   __shared__ int s_skip;
-  unsigned cur = 0;  // number of the last move taken
+  unsigned cur = 0;        // number of the last move taken
+  unsigned last_acc = 0;   // the last accepted move this helper stored
+  unsigned confirmed = 0;  // the rows this helper reads hold the accepted moves up to this one
+  // levels of this helper's fine blocks: their rows change owner from move
+  // to move (the coarse blocks of levels 2 and 3 always belong to the same
+  // helper, which stores and re-reads them itself)
+  const int bpl = (378 + NG - 1) / NG;
+  unsigned lvmask = 0;
+  for (int b = w - 1; b < nblk; b += G - 1)
+    if (b >= 72) lvmask |= 1u << (4 + (b - 72) / bpl);
   while (true) {
     const unsigned num = cur + 1;
     // wait until move `num` is posted; the stop flag is stored before the
@@ -504,6 +539,23 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     if (f == 2) return;
     cur = num;
     if (skip) continue;
+    // the speculation reads target rows: the fine-level rows of the last
+    // accepted move, stored by the helpers of those levels, must be in place
+    if (confirmed != last_acc && lvmask) {
+      if (t < 64) {
+        bool ok = spin_level_helpers(doneflag, G, lvmask, bpl, last_acc, SPIN_LIMIT);
+        if (t == 0) s_flag = ok ? 0 : 1;
+      }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int f2 = s_flag;
+      __syncthreads();
+      if (f2) {
+        if (t == 0) st_relaxed(err, 1u);
+        return;
+      }
+      confirmed = last_acc;
+    }
     if (t == 0) {
       const auto slot = glb(mb) + 8 * (num & 1);
       double m[8];
@@ -567,6 +619,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
       if (t == 0) st_relaxed(&doneflag[w], num);
+      last_acc = num;
     }
   }
 }
