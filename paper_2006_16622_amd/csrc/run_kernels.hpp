@@ -614,9 +614,14 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     if (res == 1) {
       for (int k = 0, b = w - 1; b < nblk; ++k, b += G - 1)
         accept_block_store<GS, NT>(tb, s_coarse[k], spec(k), sdst + (size_t)k * NG);
-      // every thread's rows are released by its own fence; after the
-      // barrier the flag itself needs no second release
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // The rows are agent-scope atomic stores, which write through this
+      // XCD's L2; once they have completed (the wait below) they are
+      // visible to every reader that acquires at agent scope (its L2 is
+      // invalidated). An agent-scope release fence would add a write-back
+      // of the whole L2 for plain stores, of which this workgroup makes
+      // none that another one reads.
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __syncthreads();
       if (t == 0) st_relaxed(&doneflag[w], num);
       last_acc = num;
