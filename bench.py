@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
 # they were taken on; otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "c5907181a9a9bb1de04f2afa9f3cd7894d110799f9b147bc54f1a71fe98136a2",
+    "src_sha256": "89e21a28743f56bc11ed54e1983b889b1d125887a1b0d510e05286f9c394a977",
     "steps": 200000, "warmup": 2000,
-    "fetch_kib": 76578869.5625, "fetch_scale": 2.0,
-    "write_kib": 91758462.625, "write_scale": 1.0,
+    "fetch_kib": 77727365.5, "fetch_scale": 2.0,
+    "write_kib": 91758462.5938, "write_scale": 1.0,
 }
 
 
