@@ -301,13 +301,16 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
   };
 
   // ---- far lattice quadratic term: dk = q (conj T(r') - conj T(r)), 1/2 dk.R(dk)
-  // (this thread's share; needs both lattice points)
+  // (this thread's share; needs both lattice points). dk stays in sm.dk and
+  // R(dk) replaces sm.latO: an accept of this move adds them to K and H.
   auto lattice_quad = [&]() __attribute__((always_inline)) {
     for (int s = t; s < C; s += NT) sm.dk[s] = q * sm.sgnc[s] * (sm.latN[s] - sm.latO[s]);
     __syncthreads();
     double v = 0.0;
-    lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk,
-                     [&](int s, double y) { v += sm.wdot[s] * sm.dk[s] * y; });
+    lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk, [&](int s, double y) {
+      v += sm.wdot[s] * sm.dk[s] * y;
+      sm.latO[s] = y;
+    });
     return v;
   };
   // self-interaction with the old position's images (Sec. 3.4)
@@ -803,13 +806,13 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
 // position and leaf bins (the particle to cell map of Sec. 5.2), from the
 // bin records kept in LDS (I_SLOTK, I_CNTOLD, I_CNTNEW, I_IDLAST, stash[0]).
 // Returns nonzero on bin overflow.
-template <int GS, int PM, int NT>
+template <int GS, int PM, bool REUSE = false, int NT>
 __device__ __forceinline__ int accept_bookkeeping(const Chain &ch, const Tabs &tb, const Move &mv, double dE, Lds<GS, NT> &sm) {
   const int C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
   int *ints = sm.ints;
   const double a = ch.a, q = mv.q;
-  if (g < 2) {
+  if (!REUSE && g < 2) {
     const double *r = g ? mv.rn : mv.r;
     group_harmonics<GS, PM, 1, false>(lane, tb, sm.rec, (r[0] - 0.5 * a) / a, (r[1] - 0.5 * a) / a,
                                       (r[2] - 0.5 * a) / a, 1.0, g ? sm.latN : sm.latO);
@@ -854,12 +857,22 @@ __device__ __forceinline__ int accept_bookkeeping(const Chain &ch, const Tabs &t
     ints[I_FLAG] = ovf;
   }
   __syncthreads();
-  for (int s = t; s < C; s += NT) {
-    sm.dk[s] = q * (sm.latN[s] - sm.latO[s]);
-    sm.K[s] += sm.dk[s];
+  if (REUSE) {
+    // the proposal of this move left dk in sm.dk and R(dk) in sm.latO; its
+    // conj T is the P2M term (the conjugate harmonics are a sign change per
+    // slot), so these are bit for bit the values formed below
+    for (int s = t; s < C; s += NT) {
+      sm.K[s] += sm.dk[s];
+      sm.H[s] += sm.latO[s];
+    }
+  } else {
+    for (int s = t; s < C; s += NT) {
+      sm.dk[s] = q * (sm.latN[s] - sm.latO[s]);
+      sm.K[s] += sm.dk[s];
+    }
+    __syncthreads();
+    lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk, [&](int s, double v) { sm.H[s] += v; });
   }
-  __syncthreads();
-  lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk, [&](int s, double v) { sm.H[s] += v; });
   __syncthreads();
   int ovf = ints[I_FLAG];
   __syncthreads();

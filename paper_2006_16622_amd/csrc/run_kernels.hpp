@@ -168,7 +168,7 @@ k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
         accept_mp_wg<GS, PM, NT>(ch, tb, mv, sm.rec);
       else
         accept_all_wg<GS, PM, R, NT, true>(ch, tb, mv, sm);
-      int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, po.dE, sm);
+      int ovf = accept_bookkeeping<GS, PM, !MP>(ch, tb, mv, po.dE, sm);
       if (t == 0) {
         nacc += 1;
         dEsum += po.dE;
@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
       if (prev_acc) {
         if (G == 1) accept_all_wg<GS, PM, R>(ch, tb, mv, sm);
-        int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, po.dE, sm);
+        int ovf = accept_bookkeeping<GS, PM, true>(ch, tb, mv, po.dE, sm);
         if (t == 0) {
           nacc += 1;
           dEsum += po.dE;
