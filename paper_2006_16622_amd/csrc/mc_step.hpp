@@ -599,9 +599,12 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
       }
       if (t == 0) lst[0] = __popcll(bal);
     }
-    for (int i = t; i < NG * Cs; i += NT) acc[i] = 0.0;
     __syncthreads();
-    int nv = lst[0];
+    // each group sums its candidates in registers (in candidate order) and
+    // writes its column sums once
+    const int nv = lst[0];
+    ColSum<PM> cs;
+    cs.zero();
     for (int i = g; i < nv; i += NG) {
       int cand = lst[1 + i];
       int side = cand / 27, e = cand % 27;
@@ -609,9 +612,10 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
       const double *x = side ? mv.rn : mv.r;
       double v[3];
       for (int k = 0; k < 3; ++k) v[k] = (x[k] - ((s[k] + n * w[k]) + 0.5) * h) / h;
-      group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)v[0], (R)v[1], (R)v[2],
-                                          (R)(side ? q : -q), acc + (size_t)g * Cs);
+      group_harmonics_sum<GS, PM, 2, R>(lane, tb, sm.template rec_of<R>(), (R)v[0], (R)v[1], (R)v[2],
+                                        (R)(side ? q : -q), cs);
     }
+    flush_cols<PM, false>(lane, tb, cs, acc + (size_t)g * Cs);
     __syncthreads();
     for (int k = t; k < C; k += NT) {
       double sum = 0.0;
@@ -638,13 +642,15 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
     int k = lane + j * GS;
     old[j] = k < C ? glb(it.dst)[k] : 0.0;
   }
-  group_harmonics<GS, PM, 2, false, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
-                                       (R)it.q0, buf);
-  if (it.two) {
-    __builtin_amdgcn_wave_barrier();
-    group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)it.v1[0], (R)it.v1[1], (R)it.v1[2],
-                                        (R)it.q1, buf);
-  }
+  // the one or two contributions are summed in registers, then written once
+  ColSum<PM> cs;
+  cs.zero();
+  group_harmonics_sum<GS, PM, 2, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
+                                    (R)it.q0, cs);
+  if (it.two)
+    group_harmonics_sum<GS, PM, 2, R>(lane, tb, sm.template rec_of<R>(), (R)it.v1[0], (R)it.v1[1], (R)it.v1[2],
+                                      (R)it.q1, cs);
+  flush_cols<PM, false>(lane, tb, cs, buf);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
