@@ -21,6 +21,10 @@ struct Move {
 __device__ __forceinline__ int lin3(int n, int x, int y, int z) { return x + n * (y + n * z); }
 __device__ __forceinline__ int imod(int i, int n) { return ((i % n) + n) % n; }
 __device__ __forceinline__ int ifloordiv(int i, int n) { return (i - imod(i, n)) / n; }
+// the same for n a power of two (cells per side of a level): a mask and an
+// arithmetic shift instead of integer divisions
+__device__ __forceinline__ int pmod(int i, int n) { return i & (n - 1); }
+__device__ __forceinline__ int pfloordiv(int i, int n) { return i >> __builtin_ctz((unsigned)n); }
 
 // cells of r and rn on every level, one level per thread (caller syncs)
 __device__ __forceinline__ void locate_move_par(const Chain &ch, Move &mv) {
@@ -173,8 +177,8 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
   if (t < 216) {
     const int *c = side ? mv.c1[L] : mv.c0[L];
     int b[3] = {c[0] + ee % 3 - 1, c[1] + (ee / 3) % 3 - 1, c[2] + ee / 9 - 1};
-    const int cell = lin3(nL, imod(b[0], nL), imod(b[1], nL), imod(b[2], nL));
-    const int fx = ifloordiv(b[0], nL), fy = ifloordiv(b[1], nL), fz = ifloordiv(b[2], nL);
+    const int cell = lin3(nL, pmod(b[0], nL), pmod(b[1], nL), pmod(b[2], nL));
+    const int fx = pfloordiv(b[0], nL), fy = pfloordiv(b[1], nL), fz = pfloordiv(b[2], nL);
     w = (fx + 1) + 3 * (fy + 1) + 9 * (fz + 1);
     sx = fx * a;
     sy = fy * a;
@@ -438,7 +442,7 @@ __device__ __forceinline__ bool image_in_il(const int s[3], const int c[3], int 
   int mx = 0;
   for (int k = 0; k < 3; ++k) {
     int lo = 2 * (c[k] >> 1) - 2;
-    int v = lo + imod(s[k] - lo, n);
+    int v = lo + pmod(s[k] - lo, n);
     if (v >= lo + 6 || (free_space && v != s[k])) return false;
     b[k] = v;
     int dd = v - c[k];
@@ -472,7 +476,7 @@ __device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, c
   const int oc = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
   const int8_t *o = il_off + (oc * 189 + k189) * 3;
   int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
-  int s[3] = {imod(b[0], n), imod(b[1], n), imod(b[2], n)};
+  int s[3] = {pmod(b[0], n), pmod(b[1], n), pmod(b[2], n)};
   if (ch.free_space && (b[0] != s[0] || b[1] != s[1] || b[2] != s[2])) return it;  // outside the box
   int b_other[3];
   const bool other = image_in_il(s, co, n, b_other, ch.free_space);

@@ -35,7 +35,7 @@ __device__ __forceinline__ double m2p_cell(const Chain &ch, const Tabs &tb, cons
   double v[3];
   for (int d = 0; d < 3; ++d) v[d] = (x[d] - (b[d] + 0.5) * h) / h;
   const auto src =
-      glb(ch.Mp) + ch.mp_off[l] + (size_t)lin3(n, imod(b[0], n), imod(b[1], n), imod(b[2], n)) * tb.Cs;
+      glb(ch.Mp) + ch.mp_off[l] + (size_t)lin3(n, pmod(b[0], n), pmod(b[1], n), pmod(b[2], n)) * tb.Cs;
   const int p = tb.p, m = lane;
   // the coefficients of column m, requested before the recurrence starts
   double mre[PM + 1], mim[PM + 1];

@@ -285,16 +285,20 @@ __host__ __device__ inline size_t spec_extra_bytes(int k, int NG, int Cs) {
   return (size_t)(k - 1) * NG * Cs * sizeof(double) + (size_t)k * NG * sizeof(double *);
 }
 
-// post move `num` in its mailbox slot (one thread)
+// post move `num` in its mailbox slot (one thread). The slot is written with
+// agent-scope atomic stores, which write through this XCD's L2; once they
+// have completed, the number is stored, and a helper that sees it acquires
+// at agent scope (its L2 is invalidated) before it reads the slot. A release
+// fence would add a write-back of the whole L2 for plain stores, which the
+// helpers do not read.
 __device__ __forceinline__ void post_move(double *mb, unsigned *mvseq, unsigned num, const Move &mv) {
   const auto slot = glb(mb) + 8 * (num & 1);
-  slot[0] = (double)mv.idx;
-  slot[1] = mv.q;
-  for (int k = 0; k < 3; ++k) {
-    slot[2 + k] = mv.r[k];
-    slot[5 + k] = mv.rn[k];
-  }
-  st_release(mvseq, num);
+  const double v[8] = {(double)mv.idx, mv.q, mv.r[0], mv.r[1], mv.r[2], mv.rn[0], mv.rn[1], mv.rn[2]};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) __hip_atomic_store(slot + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  st_relaxed(mvseq, num);
 }
 
 // the whole workgroup: wavefront 0 waits until every helper has finished
@@ -432,23 +436,27 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       if (t == 0) {
         int acc = !po.singular && (u < exp(-rp.beta * po.dE));
         s_acc = acc;
-        // the decision publishes no data: a relaxed store
-        if (G > 1) st_relaxed(dec, 2u * num + (unsigned)acc);
         nprop += 1;
         nsing += po.singular;
+      }
+      __syncthreads();
+      prev_acc = s_acc;
+      // the decision (a relaxed store: it publishes no data) and the traces
+      // are stored by the last wavefront, so that the wavefront that starts
+      // the next step has no store outstanding
+      if (t == NT - 64) {
+        if (G > 1) st_relaxed(dec, 2u * num + (unsigned)prev_acc);
         const int64_t o = (int64_t)c * rp.steps + step;
         if (rp.tr_idx) glb(rp.tr_idx)[o] = mv.idx;
         if (rp.tr_pos)
           for (int k = 0; k < 3; ++k) glb(rp.tr_pos)[3 * o + k] = mv.rn[k];
         if (rp.tr_dE) glb(rp.tr_dE)[o] = po.dE;
-        if (rp.tr_acc) glb(rp.tr_acc)[o] = (uint8_t)acc;
+        if (rp.tr_acc) glb(rp.tr_acc)[o] = (uint8_t)prev_acc;
         if (rp.tr_leaf) {
           int n = 1 << (ch.L - 1);
           glb(rp.tr_leaf)[o] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
         }
       }
-      __syncthreads();
-      prev_acc = s_acc;
       prev_idx = mv.idx;
       for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
       if (prev_acc) {
