@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
 # they were taken on; otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "89e21a28743f56bc11ed54e1983b889b1d125887a1b0d510e05286f9c394a977",
+    "src_sha256": "cf114b89f5be73d8fea57c6b4f0039f1d19b0baaf97b36d65ba7b44d9766b319",
     "steps": 200000, "warmup": 2000,
-    "fetch_kib": 77727365.5, "fetch_scale": 2.0,
-    "write_kib": 91758462.5938, "write_scale": 1.0,
+    "fetch_kib": 77830828.6875, "fetch_scale": 2.0,
+    "write_kib": 91775901.1875, "write_scale": 1.0,
 }
 
 
