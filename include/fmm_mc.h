@@ -161,8 +161,10 @@ typedef struct {
   int32_t status;   /* FMM_MC_OK or an error code raised on the device */
   int32_t pad;
   /* device time of the chain's proposing workgroup, microseconds (100 MHz
-   * realtime counter): proposals, its own share of accepted-move updates,
-   * and waiting for the other workgroups' shares (whole-GPU mode only) */
+   * realtime counter): proposals (without the waits), its own share of
+   * accepted-move updates, and waiting for the other workgroups' shares
+   * (whole-GPU mode only; after an accept that wait comes inside the next
+   * proposal, just before it reads the local expansions) */
   double t_propose_us, t_accept_us, t_wait_us;
 } fmm_mc_stats;
 

@@ -119,9 +119,11 @@ struct ProposeOut {
 // (the local expansions) is left out: the multipole-based variant adds its
 // own far field. When gate.active() holds, the local expansions may still be
 // being updated by other workgroups: everything that does not read them (the
-// near field, the two lattice points and the quadratic lattice term) is
-// formed first, then every thread calls gate(), which returns once the
-// expansions are current, and only then are they read.
+// near field, the harmonics of every point, the two lattice values, the
+// quadratic lattice term and the partial sums) is formed first, then every
+// thread calls gate(), which returns once the expansions are current, and
+// only then are they read. The quadratic lattice term leaves dk in sm.dk and
+// R(dk) in sm.latO for the bookkeeping of an accept of this move.
 struct NoWork {
   __device__ void operator()(int) const {}
 };

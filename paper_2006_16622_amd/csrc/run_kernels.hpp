@@ -3,15 +3,16 @@
 //  * k_run_batched: one workgroup per chain, every chain its own state; the
 //    workgroup proposes, decides and, on accept, walks every update block
 //    itself. No inter-workgroup communication: hundreds of independent
-//    chains of uneven size and depth in one launch (the paper's "several
-//    Markov chains in parallel", Sec. 6).
+//    chains of uneven size and depth in one launch (independent chains run
+//    side by side, one of the routes to parallelism named in Sec. 6).
 //  * k_run_single: one chain on many workgroups (cooperative launch, all
 //    co-resident). Workgroup 0 proposes, decides and keeps the bookkeeping;
-//    on accept it posts the move in a mailbox and the update blocks of
-//    Alg. L.2, each owning distinct target cells, are shared out over the
-//    other workgroups; workgroup 0 waits for their completion before the
-//    next proposal. The per-level work is spread as the paper suggests for
-//    parallelism (Sec. 6).
+//    it posts every move in a mailbox, and the update blocks of Alg. L.2,
+//    each owning distinct target cells, are shared out over the other
+//    workgroups, which form them speculatively and store them on accept;
+//    the next proposal waits for their completion only before it reads the
+//    local expansions. The per-level work is spread as the paper suggests
+//    for parallelism (Sec. 6).
 //
 // A step draws (idx, delta, u) from Philox4x64-10 (key = (seed, chain),
 // counter = (t, 0|1, 0, 0)) or reads them from fixed lists; the move is
@@ -209,18 +210,10 @@ __device__ __forceinline__ void st_relaxed(unsigned *p, unsigned v) {
   __hip_atomic_store(glb(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// bounded spin: returns false after `limit` ticks of the 100 MHz clock
-__device__ __forceinline__ bool spin_until_ne(unsigned *p, unsigned old, unsigned &val, uint64_t limit) {
-  uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-  while (true) {
-    val = ld_relaxed(p);
-    if (val != old) return true;
-    if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
-    __builtin_amdgcn_s_sleep(1);
-  }
-}
-// bounded spin until the counter *p has reached `target` (counters of one
-// launch stay far below 2^31, so the signed difference orders them)
+// Every spin is bounded: it returns false after `limit` ticks of the
+// 100 MHz clock.
+// spin until the counter *p has reached `target` (counters of one launch
+// stay far below 2^31, so the signed difference orders them)
 __device__ __forceinline__ bool spin_until_reached(unsigned *p, unsigned target, uint64_t limit) {
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   while (true) {
@@ -229,8 +222,8 @@ __device__ __forceinline__ bool spin_until_reached(unsigned *p, unsigned target,
     __builtin_amdgcn_s_sleep(1);
   }
 }
-// the same wait by a whole wavefront: the value is made uniform, so every
-// lane takes the same exit
+// spin by a whole wavefront until *p differs from `old`: the value is made
+// uniform, so every lane takes the same exit
 __device__ __forceinline__ bool wave_spin_until_ne(unsigned *p, unsigned old, unsigned &val, uint64_t limit) {
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   while (true) {
