@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
 # they were taken on; otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "cf114b89f5be73d8fea57c6b4f0039f1d19b0baaf97b36d65ba7b44d9766b319",
+    "src_sha256": "8c1a44d3f899b4a28b182c1a54facda8f24439c5554268c0cee365330f16e8d1",
     "steps": 200000, "warmup": 2000,
-    "fetch_kib": 77830828.6875, "fetch_scale": 2.0,
-    "write_kib": 91775901.1875, "write_scale": 1.0,
+    "fetch_kib": 78073615.4375, "fetch_scale": 2.0,
+    "write_kib": 91775901.71875, "write_scale": 1.0,
 }
 
 
