@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
 # they were taken on; otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "8c1a44d3f899b4a28b182c1a54facda8f24439c5554268c0cee365330f16e8d1",
+    "src_sha256": "3a3afeb9c2a58852c9fa98d3fce4061a3d0246fa91d2fe339dd4585b4660477c",
     "steps": 200000, "warmup": 2000,
-    "fetch_kib": 78073615.4375, "fetch_scale": 2.0,
-    "write_kib": 91775901.71875, "write_scale": 1.0,
+    "fetch_kib": 78108946.3125, "fetch_scale": 2.0,
+    "write_kib": 91775901.25, "write_scale": 1.0,
 }
 
 

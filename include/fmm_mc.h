@@ -244,6 +244,14 @@ typedef struct {
  * NULL) receives the measurements. */
 int fmm_mc_autotune(fmm_mc_t h, int64_t steps, double beta, double max_step, fmm_mc_tuning *out);
 
+/* Set the number of helper workgroups of this chain's whole-GPU runs (mode
+ * 2), the choice the autotuner makes: 0 = one helper per accept block (the
+ * untuned default); a smaller count gives each helper several blocks, and a
+ * run raises it as far as needed for the busiest helper's blocks to fit its
+ * LDS. Applies to this handle only. Returns FMM_MC_EINVAL for a null handle
+ * or a negative count. */
+int fmm_mc_set_helpers(fmm_mc_t h, int helpers);
+
 /* Release the handle (not the caller's workspace). */
 int fmm_mc_destroy(fmm_mc_t h);
 

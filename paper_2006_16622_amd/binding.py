@@ -80,6 +80,7 @@ SYMBOLS = {
     "fmm_mc_resetup": (ctypes.c_int, [_vp]),
     "fmm_mc_autotune": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                        ctypes.POINTER(Tuning)]),
+    "fmm_mc_set_helpers": (ctypes.c_int, [_vp, ctypes.c_int]),
     "fmm_mc_destroy": (ctypes.c_int, [_vp]),
     "fmm_mc_release_tables": (ctypes.c_int, []),
     "fmm_mc_last_timing": (ctypes.c_int, [_vp, _dp, ctypes.c_int]),
@@ -217,6 +218,10 @@ class Chain:
         k = t.n_helper_candidates
         return dict(m2l_rows=t.m2l_rows, helpers=t.helpers, m2l_ms=list(t.m2l_ms),
                     helper_candidates=list(t.helper_candidates[:k]), step_us=list(t.step_us[:k]))
+
+    def set_helpers(self, helpers: int):
+        """fmm_mc_set_helpers: helper workgroups of the whole-GPU run (0: one per accept block)"""
+        _check(load_library().fmm_mc_set_helpers(self._h, int(helpers)), "fmm_mc_set_helpers")
 
     def resetup(self):
         _check(load_library().fmm_mc_resetup(self._h), "fmm_mc_resetup")

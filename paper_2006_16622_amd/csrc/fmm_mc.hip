@@ -1287,6 +1287,12 @@ int fmm_mc_autotune(fmm_mc_t h, int64_t steps, double beta, double max_step, fmm
   return FMM_MC_OK;
 }
 
+int fmm_mc_set_helpers(fmm_mc_t h, int helpers) {
+  if (!h || helpers < 0) return FMM_MC_EINVAL;
+  h->helpers = helpers;
+  return FMM_MC_OK;
+}
+
 int fmm_mc_destroy(fmm_mc_t h) {
   if (!h) return FMM_MC_EINVAL;
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);

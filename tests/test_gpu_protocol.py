@@ -9,7 +9,9 @@ replays its accepted moves on an oracle whose expansions start at zero: the
 change of every local expansion of the GPU chain over the run must equal the
 oracle's sum of the P2L updates, within 1e-10 of each level's largest
 coefficient (1e-5 in mixed precision, whose update harmonics are FP32;
-a lost or doubled term is of the order of 1e-2).
+a lost or doubled term is of the order of 1e-2). The FP64 run is repeated
+with 16 and 23 helper workgroups instead of one per accept block, so that
+a helper holds several blocks, of more than one level.
 """
 import sys
 
@@ -27,14 +29,15 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-@pytest.mark.parametrize("flags", [0, 1])
-def test_consecutive_accepts_update_every_row_once(flags):
+@pytest.mark.parametrize("flags,helpers", [(0, 0), (1, 0), (0, 16), (0, 23)])
+def test_consecutive_accepts_update_every_row_once(flags, helpers):
     from paper_2006_16622_amd import Chain, run_chains
     wl = W.uniform(4000, 4, 8, 0.01, seed=101, key=61)
     steps = 3000
     gpu = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
+    gpu.set_helpers(helpers)  # 0: one helper per accept block; else blocks of several levels per helper
     before = {l: gpu.locals(l) for l in range(2, wl.depth + 2)}
-    say(f"[protocol] flags {flags}: whole-GPU run of {steps} steps")
+    say(f"[protocol] flags {flags}, helpers {helpers}: whole-GPU run of {steps} steps")
     st, tr = run_chains([gpu], steps, wl.seed, wl.beta, wl.max_step, mode=2, traces=True)
     assert st[0]["status"] == 0
     acc = tr["acc"][0]
