@@ -149,6 +149,14 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
 
   if (t >= NT - 64) early(t - (NT - 64));
 
+  // The loads stay in flight across the lattice term in the whole-GPU
+  // chain's workgroups; in the wider batched workgroup the registers this
+  // holds would spill. There, too, loaded values are not selected or masked
+  // where they are loaded (that would make the wavefront wait for them at
+  // once): every load reads a valid address, and what is not needed is left
+  // out where it is used.
+  constexpr bool overlap = NT == WG_SINGLE;
+
   // ---- the level coefficients of the points are requested first (one
   // point per group), so that their memory latency overlaps the rest
   const bool one_round = npts <= NG;
@@ -160,7 +168,10 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       int s = lane + j * GS;
-      lv0[j] = s < C ? src[s] : 0.0;
+      if constexpr (overlap)
+        lv0[j] = src[min(s, Cs - 1)];  // slots >= C are not used
+      else
+        lv0[j] = s < C ? src[s] : 0.0;
     }
   }
 
@@ -186,18 +197,18 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
     sy = fy * a;
     sz = fz * a;
     base = (size_t)cell * B;
-    cnt = (ch.free_space && w != 13) ? 0 : glb(ch.bin_cnt)[cell];  // free space: no images
+    if constexpr (overlap)
+      cnt = glb(ch.bin_cnt)[cell];
+    else
+      cnt = (ch.free_space && w != 13) ? 0 : glb(ch.bin_cnt)[cell];  // free space: no images
     id = glb(ch.bin_id)[base + j0];
     pj = ld_rec(ch.bin_p, base + j0);
     id1 = glb(ch.bin_id)[base + j0 + 4];
     pj1 = ld_rec(ch.bin_p, base + j0 + 4);
   }
-  // the loads stay in flight across the lattice term in the whole-GPU
-  // chain's workgroups; in the wider batched workgroup the registers this
-  // holds would spill
-  constexpr bool overlap = NT == WG_SINGLE;
   auto near_sum = [&]() __attribute__((always_inline)) {
     if (t >= 216) return;
+    if (overlap && ch.free_space && w != 13) cnt = 0;  // free space: no images
     if (ee == 13 && j0 == 0) ints[side ? I_CNTNEW : I_CNTOLD] = cnt;
     const double *x = side ? mv.rn : mv.r;
     for (int j = j0; j < cnt; j += 4) {
@@ -260,14 +271,20 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         int s = lane + j * GS;
-        lv[j] = s < C ? src[s] : 0.0;
+        if constexpr (overlap)
+          lv[j] = src[min(s, Cs - 1)];
+        else
+          lv[j] = s < C ? src[s] : 0.0;
       }
     } else {
       const auto gsrc = glb(src);
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         int s = lane + j * GS;
-        lv[j] = s < C ? gsrc[s] : 0.0;
+        if constexpr (overlap)
+          lv[j] = gsrc[min(s, Cs - 1)];
+        else
+          lv[j] = s < C ? gsrc[s] : 0.0;
       }
     }
   };
@@ -578,7 +595,7 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
     const double h = a / n;
     int s[3] = {s_lin % n, (s_lin / n) % n, s_lin / (n * n)};
     double *row = ch.Ld + ch.ld_off[l] + (size_t)s_lin * Cs;
-    double old = t < C ? glb(row)[t] : 0.0;  // C <= NT for the 16-lane groups
+    double old = glb(row)[min(t, Cs - 1)];  // used for t < C (C <= NT for the 16-lane groups)
     if (t < NG) dst[t] = t == 0 ? row : nullptr;
     if (t < 64) {
       bool valid = false;
@@ -646,7 +663,7 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     int k = lane + j * GS;
-    old[j] = k < C ? glb(it.dst)[k] : 0.0;
+    old[j] = glb(it.dst)[min(k, Cs - 1)];
   }
   // the one or two contributions are summed in registers, then written once
   ColSum<PM> cs;
