@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
 # they were taken on; otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "3a3afeb9c2a58852c9fa98d3fce4061a3d0246fa91d2fe339dd4585b4660477c",
+    "src_sha256": "cd0e08b0bb0669f0fa02ad5defdcc51a3dda5c44e9419650d16d6fa3b3afde00",
     "steps": 200000, "warmup": 2000,
-    "fetch_kib": 78108946.3125, "fetch_scale": 2.0,
-    "write_kib": 91775901.25, "write_scale": 1.0,
+    "fetch_kib": 78057741.25, "fetch_scale": 2.0,
+    "write_kib": 91775901.03125, "write_scale": 1.0,
 }
 
 
