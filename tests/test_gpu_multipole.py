@@ -6,7 +6,8 @@ inputs, through the C ABI.
   up to rounding) within 1e-10 of each level's largest coefficient, and the
   setup energy within 1e-10;
 * single-call proposals and accepts: dE within 1e-10 of max(|dE|, RMS dE);
-* runs on one workgroup, on the whole GPU and batched over several chains:
+* runs on one workgroup, on the whole GPU (with one helper per group of
+  far-field items, and with 7 helpers) and batched over several chains:
   indices, new positions and decisions bit-exact, dE within 1e-10, final
   positions bit-exact and multipoles within 1e-10;
 * the re-setup graph equals a fresh setup bit for bit;
@@ -120,14 +121,15 @@ def _compare_run(wl, st, tr, orc, steps, k=0):
     return ref
 
 
-@pytest.mark.parametrize("mode", [1, 2])
-def test_run_matches_oracle(mode):
+@pytest.mark.parametrize("mode,helpers", [(1, 0), (2, 0), (2, 7)])
+def test_run_matches_oracle(mode, helpers):
     from paper_2006_16622_amd import Chain, run_chains
     wl = W.uniform(1200, 3, 8, 0.05, seed=65, key=25)
     steps = 300
     orc = O.Multilevel(wl.pos, wl.q, wl.box, wl.depth, wl.p, setup="multipole")
     gpu = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=MP)
-    say(f"[mp] run mode {mode}")
+    gpu.set_helpers(helpers)  # 7: each helper evaluates many far-field items of the proposal
+    say(f"[mp] run mode {mode}, helpers {helpers}")
     st, tr = run_chains([gpu], steps, wl.seed, wl.beta, wl.max_step, mode=mode, traces=True)
     u0 = orc.energy()
     ref = _compare_run(wl, st[0], tr, orc, steps)

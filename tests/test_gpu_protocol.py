@@ -52,3 +52,13 @@ def test_consecutive_accepts_update_every_row_once(flags, helpers):
         err = np.abs(got - ref).max() / np.abs(ref).max()
         say(f"[protocol] level {level}: max |change - P2L sum| / level max = {err:.2e}")
         assert err <= (1e-5 if flags else 1e-10)
+
+
+def test_set_helpers_rejects_a_negative_count():
+    from paper_2006_16622_amd import Chain, FmmMcError
+    wl = W.uniform(300, 2, 4, 0.05, seed=102, key=62)
+    gpu = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+    with pytest.raises(FmmMcError) as e:
+        gpu.set_helpers(-1)
+    assert e.value.code == -1  # FMM_MC_EINVAL
+    gpu.set_helpers(0)
