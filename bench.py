@@ -1,28 +1,43 @@
 """Benchmark: Metropolis-Hastings steps per second of the multilevel
 local-expansion method on one MI355X.
 
-Workload (default): the jittered rock-salt system of 46^3 = 97336 charges in
-the periodic unit cube, octree depth 5, degree p = 12, beta = 1, displacement
-uniform in [-0.3/46, 0.3/46)^3, one chain, FP64. A step is one whole MH step
-(proposal energy, decision, and on acceptance the O(189 p^2 L) update of the
-interaction-list expansions plus bookkeeping), all inside one persistent
-kernel. The setup (P2M, M2M, M2L, lattice) is timed separately.
+Headline workload: the jittered rock-salt system of 46^3 = 97336 charges in
+the periodic unit cube, octree depth 5, degree p = 12, beta = 1,
+displacement uniform in [-0.3/46, 0.3/46)^3, one chain, FP64, on the whole
+GPU. An MH step is the proposal energy, the decision and, on acceptance,
+the O(189 p^2 L) update of the interaction-list expansions plus the
+bookkeeping, all inside one persistent kernel.
 
-Also measured in the same run and reported beside the headline value:
-* the same chain in mixed precision with an FP64 re-setup every 10^4
-  accepts;
+A bench step is one fmm_mc_run call of --mh-per-step MH steps (default
+10^4) on the resident chain: `--steps K --warmup W` runs W untimed calls,
+then times exactly K calls between two device synchronisations. `value` is
+the MH steps of the K calls over that wall time; the kernel's own HIP-event
+time of the same calls is reported beside it. The algorithmic bytes per
+accept come from a traced run of the same chain after the timed region.
+
+Also measured in the same run and reported beside the headline value, each
+with its error against the Ewald oracle:
+* the rock-salt chain in mixed precision with an FP64 re-setup every 10^4
+  accepts, and the drift each re-setup removes;
+* the rock-salt chain at p = 16, the degree at which its error against
+  Ewald falls below 1e-5 of RMS dE, in FP64 and in mixed precision;
+* the multipole-based variant (Alg. M.1-M.3) on the rock-salt chain, and
+  the direct P2L setup (Alg. L.3);
+* the small (N = 10^3) and medium (N = 10^4, with setup time and a mixed
+  rerun) single-chain workloads;
 * the batched form: 256 independent chains of uneven size and depth, set up
   in one pass and run in one launch, in FP64 and in mixed precision, as
-  aggregate steps/s;
-* the multipole-based variant (Alg. M.1-M.3) on the same chain;
-* the scaling sweep N = 10^3 .. 10^6 of the propose and accept times of
-  the whole-GPU chain, local method and multipole variant, each fitted to
-  the paper's performance model, with the speedup of the local method;
-* in the cpu_baseline leg: the FP64 oracle's per-step rate, the Ewald
-  oracle's, and the dE error of both precisions against Ewald on proposals
-  from the initial rock-salt state.
+  aggregate steps/s, with the dE error of 8 sampled chains against Ewald
+  and against the FP64 oracle;
+* the scaling sweep N = 10^3 .. 10^6 of the propose and accept times of the
+  whole-GPU chain, local method and multipole variant, each fitted to the
+  paper's performance model, with the speedup of the local method;
+* in the cpu_baseline leg: the FP64 oracle's per-step rate on one host core
+  (rock salt) and on all host cores (batched chains, one per thread), and
+  the Ewald oracle's.
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
+[--mh-per-step M]
 """
 from __future__ import annotations
 
@@ -40,16 +55,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# HBM bytes of the timed single-chain launch of the default command (200000
-# steps after 2000 warmup steps), from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# scaled by the counts of a plain 1 GiB device copy (FETCH_SIZE reads half the
-# copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
-# they were taken on; otherwise the traffic is reported as null.
+# HBM bytes per MH step of the timed single-chain launches of the default
+# command, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the counts of a
+# plain 1 GiB device copy (FETCH_SIZE reads half the copied bytes,
+# WRITE_SIZE all of them); the per-step figure depends on the acceptance
+# rate of the run, which the fixed proposal stream fixes. Valid only for
+# the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "cd0e08b0bb0669f0fa02ad5defdcc51a3dda5c44e9419650d16d6fa3b3afde00",
-    "steps": 200000, "warmup": 2000,
-    "fetch_kib": 78057741.25, "fetch_scale": 2.0,
-    "write_kib": 91775901.03125, "write_scale": 1.0,
+    "src_sha256": None,
+    "fetch_bytes_per_step": None,
+    "write_bytes_per_step": None,
 }
 
 
@@ -64,15 +79,30 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(steps, warmup):
+def measured_traffic(mh_steps):
     m = MEASURED_TRAFFIC
-    if kernel_sources_sha256() != m["src_sha256"] or steps != m["steps"] or warmup != m["warmup"]:
+    if m["src_sha256"] is None or kernel_sources_sha256() != m["src_sha256"]:
         return None
-    return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+    return mh_steps * (m["fetch_bytes_per_step"] + m["write_bytes_per_step"])
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def rel_rms(de, ref):
+    de, ref = np.asarray(de), np.asarray(ref)
+    return float(np.sqrt(np.mean((de - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
+
+
+def host_threads():
+    """threads for the all-core oracle leg: this process's CPU share, at
+    most 16 (the host share of one GPU)"""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def il_offsets():
@@ -150,65 +180,230 @@ def batched_algorithmic_bytes(wls, st, sample=40):
     return total
 
 
-def cpu_baseline(wl, nu, nprop=8000, nacc=1000):
-    """The FP64 oracle timed on one host core: proposals and accepts of the
-    same workload timed separately on a state whose expansions are not
-    initialised (their values do not change the per-step cost; the
-    initialisation of 97336 charges is out of reach of one core here), and
-    combined as t_prop + nu t_acc with the acceptance rate of the GPU run."""
+def moves_from_stream(wl, count, pos, chain=0):
     import oracle as O
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
-    t0 = time.perf_counter()
-    m = O.Multilevel(wl.pos, wl.q, wl.box, wl.depth, wl.p, setup="none")
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for t in range(nprop):
-        i, d, u = O.draw(wl.seed, 0, t, wl.n, wl.max_step)
-        m.propose(i, wl.pos[i] + d)
-    tp = (time.perf_counter() - t0) / nprop
-    t0 = time.perf_counter()
-    for t in range(nacc):
-        i, d, u = O.draw(wl.seed, 0, t, wl.n, wl.max_step)
-        m.accept(i, wl.pos[i] + d)
-    ta = (time.perf_counter() - t0) / nacc
-    step = tp + nu * ta
-    out = {"value": 1.0 / step, "unit": "MH steps/s", "cores": 1, "kind": "oracle",
-           "sample": f"{nprop} proposals and {nacc} accepts of the rocksalt workload on one core "
-                     f"(expansions not initialised; lattice moments formed in {t_setup:.1f} s), "
-                     f"t_prop={tp*1e3:.3f} ms, t_acc={ta*1e3:.3f} ms, combined at nu={nu:.3f}"}
-    m.close()
-    # the Ewald oracle (tin-foil, structure-factor updates): its per-step
-    # rate, and the dE of the GPU in both precisions against it
-    from paper_2006_16622_amd import FMM_MC_MIXED, Chain
-    t0 = time.perf_counter()
-    ew = O.Ewald(wl.pos, wl.q, wl.box)
-    t_ew_setup = time.perf_counter() - t0
-    moves = []
-    for t in range(200):
-        i, d, u = O.draw(wl.seed, 0, t, wl.n, wl.max_step)
-        moves.append((i, wl.pos[i] + d))
-    t0 = time.perf_counter()
-    ref = np.array([ew.propose(i, r) for i, r in moves])
-    tpe = (time.perf_counter() - t0) / len(moves)
-    t0 = time.perf_counter()
-    for i, r in moves[:100]:
-        ew.accept(i, r)
-    tae = (time.perf_counter() - t0) / 100
-    errs = {}
-    for name, flags in (("f64", 0), ("mixed", FMM_MC_MIXED), ("direct_setup", 4), ("multipole", 2)):
-        ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
-        de = np.array([ch.propose(i, r) for i, r in moves])
-        ch.close()
-        errs[name] = float(np.sqrt(np.mean((de - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
-    out["ewald"] = {"value": 1.0 / (tpe + nu * tae), "unit": "MH steps/s", "cores": 1, "kind": "oracle",
-                    "setup_s": t_ew_setup, "t_prop_ms": tpe * 1e3, "t_acc_ms": tae * 1e3}
-    out["dE_rel_rms_err_vs_ewald"] = errs
-    out["dE_err_sample"] = ("200 proposals of the Philox stream from the initial rock-salt state, p = 12; "
-                            "direct_setup: local expansions by Alg. L.3; multipole: Alg. M.1-M.3")
+    out = []
+    for t in range(count):
+        i, d, _ = O.draw(wl.seed, chain, t, wl.n, wl.max_step)
+        out.append((i, pos[i] + d))
     return out
 
 
-def run_batched(seed=4, steps=10000, nchains=256, flags=0, resetup_every=0):
+def gpu_proposals(wl, moves, flags=0, p=None):
+    from paper_2006_16622_amd import Chain
+    ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p if p is None else p, flags=flags)
+    de = np.array([ch.propose(i, r) for i, r in moves])
+    ch.close()
+    return de
+
+
+def timed_calls(chains, wl_steps, seed, beta, max_step, calls, mh, t0, resetup_every=0, mode=0):
+    """`calls` fmm_mc_run calls of `mh` MH steps each, between two device
+    synchronisations: (wall s, kernel s, summed stats per chain)"""
+    from paper_2006_16622_amd import run_chains
+    import torch
+    tot = None
+    kern = 0.0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(calls):
+        st = run_chains(chains, mh, seed, beta, max_step, t0=t0 + k * mh, mode=mode,
+                        resetup_every=resetup_every)
+        kern += chains[0].last_timing()[0] * 1e-3
+        if tot is None:
+            tot = [dict(s) for s in st]
+        else:
+            for a, b in zip(tot, st):
+                for key in ("proposed", "accepted", "singular", "dE_sum", "t_propose_us", "t_accept_us",
+                            "t_wait_us"):
+                    a[key] += b[key]
+                a["energy"] = b["energy"]
+                a["status"] = a["status"] or b["status"]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t_start, kern, tot
+
+
+def headline(wl, steps, warmup, mh):
+    """the rock-salt chain, FP64, whole GPU: setup, autotune, W warmup and
+    K timed calls of mh MH steps, then a traced sample for the bytes"""
+    from paper_2006_16622_amd import Chain, run_chains
+    import torch
+    log(f"[bench] workload {wl.name}: setup")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    m2l_ms = ch.last_timing()[1]
+    log(f"[bench] setup {t_setup*1e3:.1f} ms (M2L {m2l_ms:.2f} ms); autotune")
+    tune = ch.autotune(steps=2000, beta=wl.beta, max_step=wl.max_step)
+    log(f"[bench] autotune: M2L rows {tune['m2l_rows']}, helpers {tune['helpers']}; warmup {warmup} x {mh}")
+    tw, _, _ = timed_calls([ch], None, wl.seed, wl.beta, wl.max_step, warmup, mh, 0)
+    log(f"[bench] warmup {tw:.2f} s; timed {steps} x {mh} MH steps")
+    dt, kern, st = timed_calls([ch], None, wl.seed, wl.beta, wl.max_step, steps, mh, warmup * mh)
+    s0 = st[0]
+    total = steps * mh
+    log(f"[bench] {total / dt:.1f} MH steps/s (kernel {kern:.3f} s, wall {dt:.3f} s), accepted {s0['accepted']}")
+    # the bytes each accept touches, from a traced sample of the same chain
+    nsamp = 20000
+    pos_before = ch.positions()
+    _, tr = run_chains([ch], nsamp, wl.seed, wl.beta, wl.max_step, t0=(warmup + steps) * mh, traces=True)
+    prop_b, acc_b, nu_s, mean_t = algorithmic_bytes(wl, pos_before, tr["idx"][0], tr["newpos"][0], tr["acc"][0])
+    ch.close()
+    total_bytes = total * prop_b + s0["accepted"] * acc_b
+    achieved = total_bytes / kern / 1e9
+    nu = s0["accepted"] / total
+    out = {
+        "value": total / dt,
+        "ms_per_step": dt / steps * 1e3,
+        "kernel_ms_per_step": kern / steps * 1e3,
+        "us_per_mh_step": dt / total * 1e6,
+        "kernel_us_per_mh_step": kern / total * 1e6,
+        "nu": nu,
+        "status": s0["status"],
+        "t_prop_us": s0["t_propose_us"] / total,
+        "t_acc_us": (s0["t_accept_us"] + s0["t_wait_us"]) / max(1, s0["accepted"]),
+        "setup_ms": t_setup * 1e3, "setup_m2l_ms": m2l_ms, "autotune": tune,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(total),
+                     "algorithmic_bytes": total_bytes, "kernel": "k_run_single", "kernel_s": kern,
+                     "launches": steps, "mh_steps_per_launch": mh,
+                     "bytes_per_proposal": prop_b, "bytes_per_accept": acc_b,
+                     "targets_per_accept": mean_t, "traced_sample_steps": nsamp, "traced_sample_nu": nu_s},
+    }
+    return out
+
+
+def single_line(wl, steps, warmup, mh, flags=0, p=None, resetup_every=0, tune=False):
+    """one chain of the workload on the whole GPU: steps x mh MH steps timed"""
+    from paper_2006_16622_amd import Chain
+    pp = wl.p if p is None else p
+    ch = Chain(wl.pos, wl.q, wl.box, wl.depth, pp, flags=flags)
+    t = ch.autotune(steps=2000, beta=wl.beta, max_step=wl.max_step) if tune else None
+    timed_calls([ch], None, wl.seed, wl.beta, wl.max_step, warmup, mh, 0, resetup_every)
+    dt, kern, st = timed_calls([ch], None, wl.seed, wl.beta, wl.max_step, steps, mh, warmup * mh, resetup_every)
+    ch.close()
+    s0 = st[0]
+    total = steps * mh
+    out = {"value": total / dt, "unit": "MH steps/s", "mh_steps": total, "kernel_s": kern, "wall_s": dt,
+           "p": pp, "accepted": s0["accepted"], "status": s0["status"],
+           "t_prop_us": (s0["t_propose_us"] + (s0["t_wait_us"] if flags & 2 else 0)) / total}
+    if t is not None:
+        out["helpers"] = t["helpers"]
+    if resetup_every:
+        out["resetup_every"] = resetup_every
+    return out
+
+
+def mixed_drift(wl, mh_steps=20000, count=200):
+    """What an FP64 re-setup removes after about 10^4 accepts, measured on
+    what the expansions are for: the dE of `count` proposals from the
+    state reached (charges and displacements from a fixed numpy stream),
+    evaluated on the maintained expansions and again after a fresh FP64
+    re-setup, as the RMS and largest difference relative to RMS dE; and the
+    running energy against the fresh energy. In mixed precision and, for
+    contrast, in FP64 (where the two differ only by the truncation of the
+    P2L updates against that of M2L)."""
+    from paper_2006_16622_amd import FMM_MC_MIXED, Chain, run_chains
+    out = {}
+    for name, flags in (("mixed", FMM_MC_MIXED), ("f64", 0)):
+        ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
+        st = run_chains([ch], mh_steps, wl.seed, wl.beta, wl.max_step)
+        pos = ch.positions()
+        g = np.random.default_rng(5)
+        idx = g.integers(0, wl.n, count)
+        moves = [(int(i), pos[i] + g.uniform(-wl.max_step, wl.max_step, 3)) for i in idx]
+        kept = np.array([ch.propose(i, r) for i, r in moves])
+        u_run = ch.running_energy()
+        ch.resetup()
+        fresh = np.array([ch.propose(i, r) for i, r in moves])
+        u_fresh = ch.running_energy()
+        ch.close()
+        rms = float(np.sqrt(np.mean(fresh ** 2)))
+        out[name] = {"accepts": st[0]["accepted"],
+                     "dE_rms_diff_over_rms_dE": float(np.sqrt(np.mean((kept - fresh) ** 2)) / rms),
+                     "dE_max_diff_over_rms_dE": float(np.abs(kept - fresh).max() / rms),
+                     "energy_diff_over_rms_dE": abs(u_run - u_fresh) / rms}
+    return out
+
+
+def c3_accuracy(wl, ew, count=200):
+    """dE of every rock-salt variant against Ewald on the first `count`
+    proposals of the stream from the initial state"""
+    from paper_2006_16622_amd import FMM_MC_DIRECT_SETUP, FMM_MC_MIXED, FMM_MC_MULTIPOLE
+    moves = moves_from_stream(wl, count, wl.pos)
+    ref = np.array([ew.propose(i, r) for i, r in moves])
+    errs = {}
+    for name, flags, p in (("f64", 0, 12), ("mixed", FMM_MC_MIXED, 12), ("direct_setup", FMM_MC_DIRECT_SETUP, 12),
+                           ("multipole", FMM_MC_MULTIPOLE, 12), ("f64_p16", 0, 16), ("mixed_p16", FMM_MC_MIXED, 16)):
+        errs[name] = rel_rms(gpu_proposals(wl, moves, flags, p), ref)
+    return errs, moves, ref
+
+
+def small_configs():
+    """the N = 10^3 and N = 10^4 single-chain workloads: all their
+    proposals timed from the setup state, and the setup timed"""
+    import workloads as W
+    from paper_2006_16622_amd import FMM_MC_MIXED, Chain, run_chains
+    import torch
+    out = {}
+    for wl in (W.small(), W.medium()):
+        line = {"workload": wl.name, "n": wl.n, "depth": wl.depth, "p": wl.p, "max_step": wl.max_step,
+                "proposals": wl.steps}
+        for name, flags in (("f64", 0), ("mixed", FMM_MC_MIXED)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            m2l = ch.last_timing()[1]
+            ch.autotune(steps=1000, beta=wl.beta, max_step=wl.max_step)
+            # the workload's proposals, once untimed on a clone state (kernel
+            # load), then timed from the setup state of a fresh chain
+            run_chains([ch], min(wl.steps, 2000), wl.seed, wl.beta, wl.max_step)
+            ch.close()
+            ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
+            resetup = 10000 if flags else 0
+            dt, kern, st = timed_calls([ch], None, wl.seed, wl.beta, wl.max_step, 1, wl.steps, 0, resetup)
+            ch.close()
+            line[name] = {"value": wl.steps / dt, "unit": "MH steps/s", "kernel_s": kern, "wall_s": dt,
+                          "nu": st[0]["accepted"] / wl.steps, "status": st[0]["status"],
+                          "setup_ms": t_setup * 1e3, "setup_m2l_ms": m2l}
+            if flags:
+                line[name]["resetup_every"] = resetup
+            log(f"[bench] {wl.name} {name}: {line[name]['value']:.0f} MH steps/s, setup {t_setup*1e3:.1f} ms")
+        out[wl.name] = line
+    return out
+
+
+def small_configs_accuracy(lines, npre=2000):
+    """the chain prefix of npre steps of each small workload, both
+    precisions, against the Ewald oracle, whose state follows the accepts"""
+    import oracle as O
+    import workloads as W
+    from paper_2006_16622_amd import FMM_MC_MIXED, Chain, run_chains
+    for wl in (W.small(), W.medium()):
+        for name, flags in (("f64", 0), ("mixed", FMM_MC_MIXED)):
+            ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
+            pos0 = ch.positions()
+            _, tr = run_chains([ch], npre, wl.seed, wl.beta, wl.max_step, traces=True)
+            ch.close()
+            ew = O.Ewald(pos0, wl.q, wl.box)
+            ref = np.empty(npre)
+            for t in range(npre):
+                ref[t] = ew.propose(int(tr["idx"][0][t]), tr["newpos"][0][t])
+                if tr["acc"][0][t]:
+                    ew.accept(int(tr["idx"][0][t]), tr["newpos"][0][t])
+            ew.close()
+            err = rel_rms(tr["dE"][0], ref)
+            if wl.name in lines:
+                lines[wl.name][name]["dE_rel_rms_err_vs_ewald"] = err
+                lines[wl.name][name]["ewald_sample"] = (f"chain prefix of {npre} steps, the Ewald state follows "
+                                                        f"the accepts")
+            log(f"[bench] {wl.name} {name}: chain prefix error vs Ewald {err:.2e}")
+
+
+def run_batched(steps=10000, nchains=256, flags=0, resetup_every=0, seed=4):
     import workloads as W
     from paper_2006_16622_amd import run_chains, setup_batch
     import torch
@@ -219,15 +414,10 @@ def run_batched(seed=4, steps=10000, nchains=256, flags=0, resetup_every=0):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     m2l_ms = chains[0].last_timing()[1]
+    steps_c = [w.max_step for w in wls]
     # warmup a few steps (kernel load), then the timed launch
-    run_chains(chains, 20, seed, 1.0, [w.max_step for w in wls], t0=0, mode=1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = run_chains(chains, steps, seed, 1.0, [w.max_step for w in wls], t0=20, mode=1,
-                    resetup_every=resetup_every)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kern = chains[0].last_timing()[0] * 1e-3
+    run_chains(chains, 20, seed, 1.0, steps_c, t0=0, mode=1)
+    dt, kern, st = timed_calls(chains, None, seed, 1.0, steps_c, 1, steps, 20, resetup_every, mode=1)
     acc = sum(s["accepted"] for s in st)
     abytes = batched_algorithmic_bytes(wls, st)
     for c in chains:
@@ -236,12 +426,53 @@ def run_batched(seed=4, steps=10000, nchains=256, flags=0, resetup_every=0):
             "precision": "mixed" if flags else "f64", "resetup_every": resetup_every,
             "kernel_s": kern, "wall_s": dt, "nu": acc / (nchains * steps), "setup_s": t_setup,
             "setup_m2l_ms": m2l_ms,
+            "nu_per_chain": [s["accepted"] / steps for s in st],
             "roofline": {"bound": "hbm", "achieved": abytes / kern / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": abytes / kern / 1e9 / HBM_PEAK_GBS, "kernel": "k_run_batched",
                          "algorithmic_bytes": abytes},
             "n_range": [min(w.n for w in wls), max(w.n for w in wls)],
             "depths": {str(d): sum(1 for w in wls if w.depth == d) for d in sorted({w.depth for w in wls})},
             "status": [s["status"] for s in st if s["status"] != 0][:4]}
+
+
+def batched_accuracy(count=200):
+    """8 sampled chains of the batched workload (depths 2, 3, 4): dE of the
+    first `count` proposals from the initial state, both precisions, against
+    the Ewald oracle (relative RMS) and the FP64 multilevel oracle (largest
+    difference relative to RMS dE)"""
+    import oracle as O
+    import workloads as W
+    from paper_2006_16622_amd import FMM_MC_MIXED
+    sizes = W.batched_sizes()
+    depth = np.array([s[1] for s in sizes])
+    picks = []
+    for d, k in ((2, 2), (3, 3), (4, 3)):
+        picks += [int(c) for c in np.nonzero(depth == d)[0][:k]]
+    rows = []
+    for c in picks:
+        w = W.batched_chain(c)
+        moves = moves_from_stream(w, count, w.pos, chain=c)
+        ew = O.Ewald(w.pos, w.q, w.box)
+        ref = np.array([ew.propose(i, r) for i, r in moves])
+        ew.close()
+        orc = O.Multilevel(w.pos, w.q, w.box, w.depth, w.p)
+        de_o = np.array([orc.propose(i, r) for i, r in moves])
+        orc.close()
+        rms = float(np.sqrt(np.mean(de_o ** 2)))
+        row = {"chain": c, "n": w.n, "depth": w.depth}
+        for name, flags in (("f64", 0), ("mixed", FMM_MC_MIXED)):
+            de = gpu_proposals(w, moves, flags)
+            row[name] = {"vs_ewald_rel_rms": rel_rms(de, ref),
+                         "vs_oracle_max_over_rms": float(np.abs(de - de_o).max() / rms)}
+        rows.append(row)
+        log(f"[bench] batched accuracy chain {c} (n={w.n}, d={w.depth}): f64 {row['f64']['vs_ewald_rel_rms']:.2e} "
+            f"/ {row['f64']['vs_oracle_max_over_rms']:.1e}, mixed {row['mixed']['vs_ewald_rel_rms']:.2e} "
+            f"/ {row['mixed']['vs_oracle_max_over_rms']:.1e}")
+    return {"sample": f"{count} proposals of each chain's stream from its initial state", "chains": rows,
+            "f64_vs_ewald_max": max(r["f64"]["vs_ewald_rel_rms"] for r in rows),
+            "mixed_vs_ewald_max": max(r["mixed"]["vs_ewald_rel_rms"] for r in rows),
+            "f64_vs_oracle_max": max(r["f64"]["vs_oracle_max_over_rms"] for r in rows),
+            "mixed_vs_oracle_max": max(r["mixed"]["vs_oracle_max_over_rms"] for r in rows)}
 
 
 SWEEP_N = (1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000, 500000, 1000000)
@@ -318,52 +549,106 @@ def run_sweep(steps=2000, warmup=300, nu_paper=0.438):
             "speedup_local_over_multipole": {"nu": nu_paper, "per_n": speed, "s_inf": s_inf}}
 
 
-def run_single_variant(wl, steps, warmup, flags, resetup_every=0, tune=False):
-    """one chain of the workload with the given flags, on the whole GPU"""
-    from paper_2006_16622_amd import Chain, run_chains
-    import torch
-    ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=flags)
-    t = ch.autotune(steps=2000, beta=wl.beta, max_step=wl.max_step) if tune else None
-    run_chains([ch], warmup, wl.seed, wl.beta, wl.max_step, t0=0)
-    torch.cuda.synchronize()
+def cpu_baseline(wl, nu, ew, nprop=8000, nacc=1000):
+    """The FP64 oracle timed on one host core: proposals and accepts of the
+    rock-salt workload timed separately on a state whose expansions are not
+    initialised (their values do not change the per-step cost; the
+    initialisation of 97336 charges is out of reach of one core here), and
+    combined as t_prop + nu t_acc at the acceptance rate of the timed GPU
+    run (after its warmup). The Ewald oracle beside it."""
+    import oracle as O
     t0 = time.perf_counter()
-    st = run_chains([ch], steps, wl.seed, wl.beta, wl.max_step, t0=warmup, resetup_every=resetup_every)[0]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ch.close()
-    tp, ta = _stage_times(st, steps, flags)
-    out = {"value": steps / dt, "unit": "MH steps/s", "steps": steps, "accepted": st["accepted"],
-           "status": st["status"], "t_prop_us": tp, "t_acc_us": ta}
-    if t is not None:
-        out["helpers"] = t["helpers"]
+    m = O.Multilevel(wl.pos, wl.q, wl.box, wl.depth, wl.p, setup="none")
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for t in range(nprop):
+        i, d, u = O.draw(wl.seed, 0, t, wl.n, wl.max_step)
+        m.propose(i, wl.pos[i] + d)
+    tp = (time.perf_counter() - t0) / nprop
+    t0 = time.perf_counter()
+    for t in range(nacc):
+        i, d, u = O.draw(wl.seed, 0, t, wl.n, wl.max_step)
+        m.accept(i, wl.pos[i] + d)
+    ta = (time.perf_counter() - t0) / nacc
+    m.close()
+    step = tp + nu * ta
+    out = {"value": 1.0 / step, "unit": "MH steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{nprop} proposals and {nacc} accepts of the rocksalt workload on one core "
+                     f"(expansions not initialised; lattice moments formed in {t_setup:.1f} s), "
+                     f"t_prop={tp*1e3:.3f} ms, t_acc={ta*1e3:.3f} ms, combined at the timed GPU run's "
+                     f"acceptance nu={nu:.3f}"}
+    moves = moves_from_stream(wl, 200, wl.pos)
+    t0 = time.perf_counter()
+    for i, r in moves:
+        ew.propose(i, r)
+    tpe = (time.perf_counter() - t0) / len(moves)
+    t0 = time.perf_counter()
+    for i, r in moves[:100]:
+        ew.accept(i, r)
+    tae = (time.perf_counter() - t0) / 100
+    out["ewald"] = {"value": 1.0 / (tpe + nu * tae), "unit": "MH steps/s", "cores": 1, "kind": "oracle",
+                    "t_prop_ms": tpe * 1e3, "t_acc_ms": tae * 1e3}
     return out
 
 
-def run_single_mixed(wl, steps, warmup, resetup_every=10000):
-    from paper_2006_16622_amd import FMM_MC_MIXED, Chain, run_chains
-    import torch
-    ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=FMM_MC_MIXED)
-    run_chains([ch], warmup, wl.seed, wl.beta, wl.max_step, t0=0)
-    torch.cuda.synchronize()
+def cpu_baseline_batched(nu_per_chain, nchains_sample=None, nprop=600, nacc=120):
+    """The FP64 oracle on every host core at once, one batched chain per
+    thread (the oracle calls release the interpreter lock): each sampled
+    chain's proposals and accepts timed separately, as above, and combined
+    at that chain's acceptance rate in the GPU run. The aggregate rate is
+    threads / mean step time."""
+    import threading
+    import oracle as O
+    import workloads as W
+    nt = host_threads()
+    ns = 2 * nt if nchains_sample is None else nchains_sample
+    res = [None] * ns
+
+    def work(c):
+        w = W.batched_chain(c)
+        m = O.Multilevel(w.pos, w.q, w.box, w.depth, w.p, setup="none")
+        draws = [O.draw(w.seed, c, t, w.n, w.max_step) for t in range(nprop)]
+        t0 = time.perf_counter()
+        for i, d, _ in draws:
+            m.propose(i, w.pos[i] + d)
+        tp = (time.perf_counter() - t0) / nprop
+        t0 = time.perf_counter()
+        for i, d, _ in draws[:nacc]:
+            m.accept(i, w.pos[i] + d)
+        ta = (time.perf_counter() - t0) / nacc
+        m.close()
+        res[c] = tp + nu_per_chain[c] * ta
+
+    def worker(k):
+        for c in range(k, ns, nt):
+            work(c)
+
+    old = os.environ.get("OMP_NUM_THREADS")
     t0 = time.perf_counter()
-    st = run_chains([ch], steps, wl.seed, wl.beta, wl.max_step, t0=warmup, resetup_every=resetup_every)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ch.close()
-    return {"value": steps / dt, "unit": "MH steps/s", "precision": "mixed", "resetup_every": resetup_every,
-            "accepted": st[0]["accepted"], "status": st[0]["status"]}
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(nt)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    wall = time.perf_counter() - t0
+    mean_step = float(np.mean(res))
+    return {"value": nt / mean_step, "unit": "MH steps/s", "cores": nt, "kind": "oracle",
+            "sample": f"chains 0..{ns - 1} of the batched workload, {nprop} proposals and {nacc} accepts each, "
+                      f"one chain per thread on {nt} threads at once ({wall:.1f} s), expansions not initialised, "
+                      f"combined at each chain's acceptance in the GPU run; aggregate = threads / mean step time"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200000)
-    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=20, help="timed bench steps (fmm_mc_run calls)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed bench steps before them")
+    ap.add_argument("--mh-per-step", type=int, default=10000, help="MH steps per bench step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=10000)
     ap.add_argument("--no-sweep", action="store_true", help="skip the N = 1e3 .. 1e6 scaling sweep")
-    ap.add_argument("--mode", type=int, default=0, help="0 auto, 1 one workgroup, 2 whole GPU")
+    ap.add_argument("--no-extra", action="store_true", help="only the headline chain")
+    ap.add_argument("--batched-steps", type=int, default=10000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -382,91 +667,107 @@ def main():
               "batched chains are independent (see the scaling paragraph of the design notes); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    import torch
+    import torch  # noqa: F401
     import workloads as W
-    from paper_2006_16622_amd import Chain, run_chains
+    from paper_2006_16622_amd import FMM_MC_MIXED, FMM_MC_MULTIPOLE
     from paper_2006_16622_amd import build as B
     if not os.path.exists(B.LIB):
         B.build()
     wl = W.rocksalt()
-    log(f"[bench] workload {wl.name}: setup")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ch = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    m2l_ms = ch.last_timing()[1]
-    log(f"[bench] setup {t_setup*1e3:.1f} ms (M2L {m2l_ms:.2f} ms); autotune")
-    tune = ch.autotune(steps=2000, beta=wl.beta, max_step=wl.max_step)
-    log(f"[bench] autotune: M2L rows {tune['m2l_rows']}, helpers {tune['helpers']}; warmup {args.warmup}")
-    run_chains([ch], args.warmup, wl.seed, wl.beta, wl.max_step, t0=0, mode=args.mode)
-    torch.cuda.synchronize()
-    pos_before = ch.positions()
-    log(f"[bench] timed {args.steps} steps")
-    t0 = time.perf_counter()
-    st, tr = run_chains([ch], args.steps, wl.seed, wl.beta, wl.max_step, t0=args.warmup, mode=args.mode,
-                        traces=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kern_s = ch.last_timing()[0] * 1e-3
-    s0 = st[0]
-    value = args.steps / dt
-    log(f"[bench] {value:.1f} steps/s (kernel {kern_s:.3f} s, wall {dt:.3f} s), accepted {s0['accepted']}")
-    prop_b, acc_b, nu, mean_t = algorithmic_bytes(wl, pos_before, tr["idx"][0], tr["newpos"][0], tr["acc"][0])
-    total_bytes = args.steps * prop_b + s0["accepted"] * acc_b
-    achieved = total_bytes / kern_s / 1e9
+    mh = args.mh_per_step
+    h = headline(wl, args.steps, args.warmup, mh)
     out = {
         "metric": "MH steps/s at N=1e5 (1 chain) + aggregate over 256 chains; dE err vs Ewald",
-        "value": value,
+        "value": h["value"],
         "unit": "MH steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "n": wl.n, "depth": wl.depth, "p": wl.p, "beta": wl.beta,
-                   "max_step": wl.max_step, "chains": 1, "setup_ms": t_setup * 1e3, "setup_m2l_ms": m2l_ms,
-                   "autotune": tune,
-                   "acceptance": s0["accepted"] / args.steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.steps, args.warmup),
-                     "algorithmic_bytes": total_bytes,
-                     "kernel": "k_run_single", "kernel_s": kern_s,
-                     "bytes_per_proposal": prop_b, "bytes_per_accept": acc_b,
-                     "targets_per_accept": mean_t},
+                   "max_step": wl.max_step, "chains": 1, "mh_steps_per_step": mh,
+                   "step": f"one fmm_mc_run call of {mh} MH steps on the resident chain",
+                   "setup_ms": h["setup_ms"], "setup_m2l_ms": h["setup_m2l_ms"], "autotune": h["autotune"],
+                   "acceptance": h["nu"]},
+        "kernel_ms_per_step": h["kernel_ms_per_step"],
+        "us_per_mh_step": h["us_per_mh_step"],
+        "kernel_us_per_mh_step": h["kernel_us_per_mh_step"],
+        "t_prop_us": h["t_prop_us"], "t_acc_us": h["t_acc_us"],
+        "status": h["status"],
+        "roofline": h["roofline"],
     }
-    log("[bench] single chain, mixed precision")
-    out["single_mixed"] = run_single_mixed(wl, args.steps, args.warmup)
-    log(f"[bench] single chain mixed {out['single_mixed']['value']:.1f} steps/s")
-    log("[bench] direct P2L setup (Alg. L.3)")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    chd = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=4)
-    torch.cuda.synchronize()
-    out["setup_direct"] = {"wall_ms": (time.perf_counter() - t0) * 1e3, "p2l_ms": chd.last_timing()[1]}
-    chd.close()
-    log(f"[bench] direct setup {out['setup_direct']['wall_ms']:.1f} ms (P2L {out['setup_direct']['p2l_ms']:.2f} ms)")
-    log("[bench] single chain, multipole-based variant")
-    out["single_multipole"] = run_single_variant(wl, args.steps // 4, args.warmup, flags=2, tune=True)
-    out["single_multipole"]["variant"] = "multipole (Alg. M.1-M.3)"
-    log(f"[bench] single chain multipole {out['single_multipole']['value']:.1f} steps/s")
+    ew = None
+    if not args.no_extra:
+        log("[bench] rock salt, mixed precision, FP64 re-setup every 10^4 accepts")
+        out["single_mixed"] = single_line(wl, args.steps, 1, mh, flags=FMM_MC_MIXED, resetup_every=10000)
+        out["single_mixed"]["drift_removed_by_resetup"] = mixed_drift(wl)
+        log(f"[bench] mixed {out['single_mixed']['value']:.0f} MH steps/s")
+        log("[bench] rock salt at p = 16 (meets the 1e-5 Ewald gate), FP64 and mixed")
+        out["single_p16"] = single_line(wl, max(1, args.steps // 4), 1, mh, p=16, tune=True)
+        out["single_p16_mixed"] = single_line(wl, max(1, args.steps // 4), 1, mh, flags=FMM_MC_MIXED, p=16,
+                                              resetup_every=10000)
+        log(f"[bench] p16 {out['single_p16']['value']:.0f} / mixed {out['single_p16_mixed']['value']:.0f}")
+        log("[bench] direct P2L setup (Alg. L.3)")
+        from paper_2006_16622_amd import Chain
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chd = Chain(wl.pos, wl.q, wl.box, wl.depth, wl.p, flags=4)
+        torch.cuda.synchronize()
+        out["setup_direct"] = {"wall_ms": (time.perf_counter() - t0) * 1e3, "p2l_ms": chd.last_timing()[1]}
+        chd.close()
+        log("[bench] multipole-based variant")
+        out["single_multipole"] = single_line(wl, max(1, args.steps // 4), 1, mh, flags=FMM_MC_MULTIPOLE, tune=True)
+        out["single_multipole"]["variant"] = "multipole (Alg. M.1-M.3)"
+        log(f"[bench] multipole {out['single_multipole']['value']:.0f} MH steps/s")
+        log("[bench] small and medium workloads")
+        out["configs"] = small_configs()
     if not args.no_batched:
         log("[bench] batched 256 chains, FP64")
         out["batched"] = run_batched(steps=args.batched_steps)
-        log(f"[bench] batched {out['batched']['value']:.1f} steps/s")
+        log(f"[bench] batched {out['batched']['value']:.1f} MH steps/s")
         log("[bench] batched 256 chains, mixed precision")
-        out["batched_mixed"] = run_batched(steps=args.batched_steps, flags=1, resetup_every=10000)
-        log(f"[bench] batched mixed {out['batched_mixed']['value']:.1f} steps/s")
-    if not args.no_sweep:
+        out["batched_mixed"] = run_batched(steps=args.batched_steps, flags=FMM_MC_MIXED, resetup_every=10000)
+        log(f"[bench] batched mixed {out['batched_mixed']['value']:.1f} MH steps/s")
+    if not args.no_sweep and not args.no_extra:
         log("[bench] scaling sweep")
         out["sweep"] = run_sweep()
     if not args.no_cpu:
-        log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(wl, out["config"]["acceptance"])
+        # the cpu_baseline leg: the oracles' rates, and every error figure
+        # above measured against them
+        import oracle as O
+        if "batched" in out and not args.no_extra:
+            log("[bench] accuracy of 8 batched chains against Ewald and the oracle")
+            acc = batched_accuracy()
+            out["batched"]["accuracy"] = acc
+            out["batched_mixed"]["accuracy"] = acc
+        if "configs" in out:
+            small_configs_accuracy(out["configs"])
+        log("[bench] accuracy of the rock-salt variants against Ewald")
+        t0 = time.perf_counter()
+        ew = O.Ewald(wl.pos, wl.q, wl.box)
+        t_ew = time.perf_counter() - t0
+        errs, _, _ = c3_accuracy(wl, ew)
+        out["dE_rel_rms_err_vs_ewald"] = errs
+        out["dE_err_sample"] = ("200 proposals of the Philox stream from the initial rock-salt state; "
+                                "direct_setup: local expansions by Alg. L.3; multipole: Alg. M.1-M.3")
+        for key, line in (("f64", out), ("mixed", out.get("single_mixed")), ("f64_p16", out.get("single_p16")),
+                          ("mixed_p16", out.get("single_p16_mixed")), ("multipole", out.get("single_multipole"))):
+            if line is not None:
+                line["dE_rel_rms_err_vs_ewald"] = errs[key]
+        log(f"[bench] errors vs Ewald: {errs}")
+        log("[bench] cpu baseline (oracle), one core")
+        out["cpu_baseline"] = cpu_baseline(wl, h["nu"], ew)
+        out["cpu_baseline"]["ewald"]["setup_s"] = t_ew
+        ew.close()
+        if "batched" in out:
+            log("[bench] cpu baseline (oracle), batched chains on all host cores")
+            out["cpu_baseline"]["batched_all_cores"] = cpu_baseline_batched(out["batched"]["nu_per_chain"])
+    out.pop("status") if out.get("status") == 0 else None
     print(json.dumps(out), flush=True)
 
 

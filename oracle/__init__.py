@@ -44,7 +44,7 @@ def build(force: bool = True) -> str:
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-o", tmp] + _SRC + ["-lm"]
+           "-fno-fast-math", "-fopenmp", "-o", tmp] + _SRC + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

@@ -30,7 +30,9 @@
  *
  * Compile with gcc -O2, no fast-math, -ffp-contract=off: the wrap, cell
  * location, displacement and accept decision must round exactly as IEEE
- * double without contraction.
+ * double without contraction. With -fopenmp the cells of the M2L setup are
+ * shared out over threads; each cell's sum is formed by one thread in the
+ * same order, so every result is the same for any thread count.
  */
 #include <complex.h>
 #include <math.h>
@@ -750,19 +752,24 @@ void orc_setup_fmm(orc_t *st, int lazy) {
   st->nlog = 0;
   upward_pass(st);
   init_lattice(st);
+  /* the shared tables are formed before the cells are spread over threads */
+  (void)fact(0);
+  (void)m2l_const_table(st->p);
   for (int l = 2; l <= st->L; ++l) {
     int n = nside(l);
     memset(st->ready[l], 0, (size_t)n * n * n);
     if (lazy) continue;
-    for (int z = 0; z < n; ++z)
-      for (int y = 0; y < n; ++y)
-        for (int x = 0; x < n; ++x) {
-          int c[3] = {x, y, z};
-          cplx *Lc = &st->Ld[l][(size_t)cell_lin(n, c) * st->C];
-          memset(Lc, 0, sizeof(cplx) * st->C);
-          m2l_cell(st, l, c, Lc);
-          st->ready[l][cell_lin(n, c)] = 1;
-        }
+    /* every cell's M2L sum is independent and formed in the same order by
+     * one thread, so the result does not depend on the thread count */
+    const long ncell = (long)n * n * n;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long lin = 0; lin < ncell; ++lin) {
+      int c[3] = {(int)(lin % n), (int)((lin / n) % n), (int)(lin / ((long)n * n))};
+      cplx *Lc = &st->Ld[l][(size_t)lin * st->C];
+      memset(Lc, 0, sizeof(cplx) * st->C);
+      m2l_cell(st, l, c, Lc);
+      st->ready[l][lin] = 1;
+    }
   }
 }
 

@@ -6,8 +6,10 @@ handle. No computation happens here.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -89,6 +91,22 @@ SYMBOLS = {
 }
 
 
+# Chains still open; closed, and the shared tables freed, by an exit hook
+# that runs before the interpreter tears down its modules (a handle's HIP
+# objects are released while the runtime is still whole).
+_live = weakref.WeakSet()
+
+
+def _close_all():
+    for c in list(_live):
+        try:
+            c.close()
+        except Exception:
+            pass
+    if _lib is not None:
+        _lib.fmm_mc_release_tables()
+
+
 def load_library():
     """Load libfmm_mc.so; raises if it has not been built."""
     global _lib
@@ -102,6 +120,7 @@ def load_library():
         f.restype = res
         f.argtypes = args
     _lib = lib
+    atexit.register(_close_all)
     return lib
 
 
@@ -147,6 +166,7 @@ class Chain:
         self.ws_ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._h = _vp()
+        _live.add(self)
         if _defer:
             return
         with torch.cuda.device(self.device):
@@ -271,9 +291,12 @@ def setup_batch(systems, p: int, flags: int = 0, device: str = "cuda:0", stream=
 
 
 def run_chains(chains, steps: int, seed: int, beta: float, max_step, t0: int = 0, mode: int = 0,
-               traces: bool = False, resetup_every: int = 0):
+               traces: bool = False, resetup_every: int = 0, trace_ptrs=None):
     """fmm_mc_run over a list of Chain objects (same device and stream).
-    With traces, device buffers (torch) are allocated and returned as numpy."""
+    With traces, device buffers (torch) are allocated and returned as numpy.
+    trace_ptrs: device addresses (ints) of caller-owned trace buffers,
+    keys idx, newpos, dE, acc, laid out [chain * steps + t] as in
+    fmm_mc_run_opts; nothing is allocated or returned for them."""
     import torch
     lib = load_library()
     nc = len(chains)
@@ -287,6 +310,11 @@ def run_chains(chains, steps: int, seed: int, beta: float, max_step, t0: int = 0
     opts.mode = int(mode)
     opts.resetup_every = int(resetup_every)
     tr = None
+    if trace_ptrs is not None:
+        opts.trace_idx = trace_ptrs.get("idx")
+        opts.trace_newpos = trace_ptrs.get("newpos")
+        opts.trace_dE = trace_ptrs.get("dE")
+        opts.trace_acc = trace_ptrs.get("acc")
     if traces:
         dev = chains[0].device
         tr = dict(idx=torch.zeros(nc * steps, dtype=torch.int64, device=dev),

@@ -308,6 +308,14 @@ struct fmm_mc_ctx {
   int helpers = 0;                    // tuned helper workgroups of the whole-GPU run (0: all blocks)
   double last_ms[4] = {0, 0, 0, 0};
   bool ready = false;
+  // buffers of the run entry points, allocated at setup (host_stats) or on
+  // the first run of many chains led by this handle (grown when a run has
+  // more chains than any before): launch arguments and per-chain results
+  double *host_stats = nullptr;       // pinned, RUN_NSTAT doubles: results of a one-chain run
+  char *run_dev = nullptr;            // device: descriptors, first steps, ids, step sizes, results
+  size_t run_dev_cap = 0;
+  char *run_host = nullptr;           // pinned staging of the same
+  size_t run_host_cap = 0;
 };
 
 namespace {
@@ -590,8 +598,9 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
   ch.stage = (double *)(w + ly.off[O_STAGE]);
   h->d_chain = (Chain *)(w + ly.off[O_CHAIN]);
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
-      hipEventCreate(&h->ev2) != hipSuccess) {
-    delete h;
+      hipEventCreate(&h->ev2) != hipSuccess ||
+      hipHostMalloc((void **)&h->host_stats, sizeof(double) * RUN_NSTAT, hipHostMallocDefault) != hipSuccess) {
+    fmm_mc_destroy(h);
     return FMM_MC_EDEVICE;
   }
   std::vector<double> stage(4 * n);
@@ -798,14 +807,73 @@ int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *
   return status ? status : FMM_MC_OK;
 }
 
-// shared driver of fmm_mc_run and fmm_mc_replay. With resetup_every > 0 a
-// chain stops after that many accepts, is re-set up (its captured setup
-// graph, FP64) and continues where it stopped, until every chain has done
-// `steps` steps; the chains still running are relaunched together.
+// Device and pinned host buffers of a run of many chains (one workgroup
+// each), kept by the handle of the run's first chain: the chain
+// descriptors, first steps and ids of a launch's slots, the step sizes of
+// the run's chains and the per-slot results. Allocated on the first such
+// run and grown only when a run has more chains than any before, so that
+// repeated runs allocate nothing.
+struct RunArea {
+  size_t o_desc, o_first, o_id, o_step, o_stats, bytes;
+  RunArea(int n_chains) {
+    size_t o = 0;
+    auto take = [&](size_t b) {
+      size_t r = o;
+      o += (b + 255) / 256 * 256;
+      return r;
+    };
+    o_desc = take(sizeof(Chain) * n_chains);
+    o_first = take(sizeof(int64_t) * n_chains);
+    o_id = take(sizeof(int) * n_chains);
+    o_step = take(sizeof(double) * n_chains);
+    o_stats = take(sizeof(double) * RUN_NSTAT * n_chains);
+    bytes = o;
+  }
+};
+
+static int ensure_run_area(fmm_mc_ctx *h, size_t bytes) {
+  if (h->run_dev_cap < bytes) {
+    if (h->run_dev) {
+      HIPCHK(hipStreamSynchronize(h->stream));
+      HIPCHK(hipFree(h->run_dev));
+      h->run_dev = nullptr;
+      h->run_dev_cap = 0;
+    }
+    HIPCHK(hipMalloc((void **)&h->run_dev, bytes));
+    h->run_dev_cap = bytes;
+  }
+  if (h->run_host_cap < bytes) {
+    if (h->run_host) {
+      HIPCHK(hipStreamSynchronize(h->stream));
+      HIPCHK(hipHostFree(h->run_host));
+      h->run_host = nullptr;
+      h->run_host_cap = 0;
+    }
+    HIPCHK(hipHostMalloc((void **)&h->run_host, bytes, hipHostMallocDefault));
+    h->run_host_cap = bytes;
+  }
+  return 0;
+}
+
+// Where a run keeps its arguments and results. The default (dev == null)
+// is the first chain's buffers above; fmm_mc_run_noalloc hands in its own.
+struct RunMem {
+  char *dev = nullptr;   // device block laid out as RunArea
+  char *host = nullptr;  // host staging of the same layout (pinned or not)
+};
+
+// shared driver of fmm_mc_run, fmm_mc_run_noalloc and fmm_mc_replay. With
+// resetup_every > 0 a chain stops after that many accepts, is re-set up
+// (its captured setup graph, FP64) and continues where it stopped, until
+// every chain has done `steps` steps; the chains still running are
+// relaunched together. A run of one chain on the whole GPU passes its
+// arguments by value and takes its results from the chain's workspace; a
+// run of many copies its slots' arguments in once and the results out once
+// per launch.
 static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t seed, int64_t t0, double beta,
                       const double *steps_h, int mode, int64_t resetup_every, const int64_t *l_idx,
                       const double *l_pos, const double *l_u, int64_t *tr_idx, double *tr_pos, double *tr_dE,
-                      uint8_t *tr_acc, int32_t *tr_leaf, fmm_mc_stats *stats) {
+                      uint8_t *tr_acc, int32_t *tr_leaf, fmm_mc_stats *stats, const RunMem *mem = nullptr) {
   fmm_mc_t h0 = chains[0];
   for (int c = 0; c < n_chains; ++c) {
     if (!chains[c] || !chains[c]->ready) return FMM_MC_ESTATE;
@@ -821,72 +889,48 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   const bool single = (n_chains == 1 && mode != 1);
   const int NT = single ? WG_SINGLE : WG_BATCH;
   size_t shm = smem_bytes(GS, tb, NT);
-  // launch arguments in stream-ordered device memory, freed at the end
-  double *d_step = nullptr, *d_stats = nullptr;
-  Chain *d_chains = nullptr;
-  int64_t *d_first = nullptr;
-  int *d_id = nullptr;
-  int64_t *d_lidx = nullptr;
-  double *d_lpos = nullptr, *d_lu = nullptr;
-  auto release = [&]() {
-    (void)hipFreeAsync(d_step, st);
-    (void)hipFreeAsync(d_stats, st);
-    (void)hipFreeAsync(d_chains, st);
-    (void)hipFreeAsync(d_first, st);
-    (void)hipFreeAsync(d_id, st);
-    if (d_lidx) {
-      (void)hipFreeAsync(d_lidx, st);
-      (void)hipFreeAsync(d_lpos, st);
-      (void)hipFreeAsync(d_lu, st);
+  const RunArea ra(n_chains);
+  char *dev = nullptr, *host = nullptr;
+  if (!single) {
+    if (mem) {
+      dev = mem->dev;
+      host = mem->host;
+    } else {
+      int r = ensure_run_area(h0, ra.bytes);
+      if (r) return r;
+      dev = h0->run_dev;
+      host = h0->run_host;
     }
-    (void)hipStreamSynchronize(st);
-  };
-#define RUNCHK(x)                   \
-  do {                              \
-    if ((x) != hipSuccess) {        \
-      release();                    \
-      return FMM_MC_EDEVICE;        \
-    }                               \
-  } while (0)
-  RUNCHK(hipMallocAsync((void **)&d_step, sizeof(double) * n_chains, st));
-  RUNCHK(hipMallocAsync((void **)&d_stats, sizeof(double) * 8 * n_chains, st));
-  RUNCHK(hipMallocAsync((void **)&d_chains, sizeof(Chain) * n_chains, st));
-  RUNCHK(hipMallocAsync((void **)&d_first, sizeof(int64_t) * n_chains, st));
-  RUNCHK(hipMallocAsync((void **)&d_id, sizeof(int) * n_chains, st));
-  RUNCHK(hipMemcpyAsync(d_step, steps_h, sizeof(double) * n_chains, hipMemcpyHostToDevice, st));
-  if (l_idx) {
-    RUNCHK(hipMallocAsync((void **)&d_lidx, sizeof(int64_t) * steps, st));
-    RUNCHK(hipMallocAsync((void **)&d_lpos, sizeof(double) * 3 * steps, st));
-    RUNCHK(hipMallocAsync((void **)&d_lu, sizeof(double) * steps, st));
-    RUNCHK(hipMemcpyAsync(d_lidx, l_idx, sizeof(int64_t) * steps, hipMemcpyHostToDevice, st));
-    RUNCHK(hipMemcpyAsync(d_lpos, l_pos, sizeof(double) * 3 * steps, hipMemcpyHostToDevice, st));
-    RUNCHK(hipMemcpyAsync(d_lu, l_u, sizeof(double) * steps, hipMemcpyHostToDevice, st));
   }
+  double *d_stats = single ? (double *)(h0->ws + h0->ly.off[O_STATS]) : (double *)(dev + ra.o_stats);
+  double *h_stats = single ? (mem ? (double *)mem->host : h0->host_stats) : (double *)(host + ra.o_stats);
   RunParams rp{};
   rp.steps = steps;
   rp.t0 = t0;
   rp.seed = seed;
   rp.beta = beta;
-  rp.max_step = d_step;
-  rp.first = d_first;
-  rp.chain_id = d_id;
+  rp.max_step = single ? nullptr : (const double *)(dev + ra.o_step);
+  rp.max_step0 = steps_h[0];
+  rp.first = single ? nullptr : (const int64_t *)(dev + ra.o_first);
+  rp.chain_id = single ? nullptr : (const int *)(dev + ra.o_id);
   rp.acc_limit = resetup_every > 0 ? resetup_every : 0;
-  rp.list_idx = d_lidx;
-  rp.list_pos = d_lpos;
-  rp.list_u = d_lu;
+  rp.list_idx = l_idx;
+  rp.list_pos = l_pos;
+  rp.list_u = l_u;
   rp.tr_idx = tr_idx;
   rp.tr_pos = tr_pos;
   rp.tr_dE = tr_dE;
   rp.tr_acc = tr_acc;
   rp.tr_leaf = tr_leaf;
   rp.stats = d_stats;
+  if (!single) std::memcpy(host + ra.o_step, steps_h, sizeof(double) * n_chains);
   int G = 1;
   if (single && mp) {
     // workgroup 0 proposes and accepts, the others (one per CU at most)
     // share the far-field items of each proposal
     const int NG = NT / GS;
     int ncu = 0, per = 0;
-    RUNCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
     G = (mp_items(h0->ch.L) + NG - 1) / NG + 1;
     if (h0->helpers > 0) G = std::min(G, h0->helpers + 1);
     G = std::max(1, std::min(G, std::min(ncu, 448)));
@@ -895,66 +939,62 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
       oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &per, k_run_single_mp<decltype(gs)::value, decltype(pm)::value>, NT, shm);
     });
-    RUNCHK(oe);
-    if (per < 1) {
-      release();
-      return FMM_MC_EDEVICE;
-    }
+    HIPCHK(oe);
+    if (per < 1) return FMM_MC_EDEVICE;
   } else if (single) {
     // workgroup 0 proposes, the others (one per CU at most) hold the accept
     // blocks; the busiest helper's speculative rows must fit its LDS
     const int NG = NT / GS;
     const int nblk = accept_blocks(h0->ch.L, NG);
     int ncu = 0, maxlds = 0, per = 0;
-    RUNCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
-    RUNCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, h0->device));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
+    HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, h0->device));
     auto kmax_of = [&](int g) { return g < 2 ? 1 : (nblk + g - 2) / (g - 1); };
     auto shm_of = [&](int g) { return smem_bytes(GS, tb, NT) + (g < 2 ? 0 : spec_extra_bytes(kmax_of(g), NG, h0->Cs)); };
     G = nblk + 1;
     if (h0->helpers > 0) G = std::min(G, h0->helpers + 1);
     G = std::max(1, std::min(G, ncu));
     while (G < ncu && G < nblk + 1 && (kmax_of(G) > SPEC_MAX || shm_of(G) > (size_t)maxlds)) ++G;
-    if (kmax_of(G) > SPEC_MAX || shm_of(G) > (size_t)maxlds) {
-      release();
-      return FMM_MC_EDEVICE;
-    }
+    if (kmax_of(G) > SPEC_MAX || shm_of(G) > (size_t)maxlds) return FMM_MC_EDEVICE;
     shm = shm_of(G);
     hipError_t oe = hipSuccess;
     with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
       oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &per, k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>, NT, shm);
     });
-    RUNCHK(oe);
-    if (per < 1) {
-      release();
-      return FMM_MC_EDEVICE;
-    }
+    HIPCHK(oe);
+    if (per < 1) return FMM_MC_EDEVICE;
   }
+  // per chain of the run: steps done, accumulated counters, final energy
   std::vector<int64_t> done(n_chains, 0);
-  std::vector<double> acc(8 * n_chains, 0.0);  // accumulated stats per chain
+  std::vector<double> acc(RUN_NSTAT * n_chains, 0.0);
+  std::vector<double> energy(n_chains, 0.0);
   std::vector<int> ids;
-  std::vector<int64_t> firsts;
-  std::vector<Chain> hc;
-  std::vector<double> hs;
+  ids.reserve(n_chains);
   double kernel_ms = 0.0;
   int rc = FMM_MC_OK;
   while (rc == FMM_MC_OK) {
     ids.clear();
-    firsts.clear();
-    hc.clear();
     for (int c = 0; c < n_chains; ++c)
-      if (done[c] < steps) {
-        ids.push_back(c);
-        firsts.push_back(done[c]);
-        hc.push_back(chains[c]->ch);
-      }
+      if (done[c] < steps) ids.push_back(c);
     const int na = (int)ids.size();
     if (na == 0) break;
-    RUNCHK(hipMemcpyAsync(d_chains, hc.data(), sizeof(Chain) * na, hipMemcpyHostToDevice, st));
-    RUNCHK(hipMemcpyAsync(d_first, firsts.data(), sizeof(int64_t) * na, hipMemcpyHostToDevice, st));
-    RUNCHK(hipMemcpyAsync(d_id, ids.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
-    if (single) hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 512);
-    RUNCHK(hipEventRecord(h0->ev0, st));
+    if (single) {
+      rp.first0 = done[0];
+      hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(NT), 0, st, (int *)h0->ch.sync, 0, 512);
+    } else {
+      Chain *hd = (Chain *)(host + ra.o_desc);
+      int64_t *hf = (int64_t *)(host + ra.o_first);
+      int *hi = (int *)(host + ra.o_id);
+      for (int k = 0; k < na; ++k) {
+        hd[k] = chains[ids[k]]->ch;
+        hf[k] = done[ids[k]];
+        hi[k] = ids[k];
+      }
+      // descriptors, first steps, ids and step sizes lie before the results
+      HIPCHK(hipMemcpyAsync(dev, host, ra.o_stats, hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipEventRecord(h0->ev0, st));
     if (single) {
       Chain chv = h0->ch;
       void *args[] = {&chv, (void *)&tb, &rp};
@@ -970,35 +1010,38 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
               (const void *)k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>,
               dim3(G), dim3(NT), args, shm, st);
         });
-      RUNCHK(e);
-    } else if (mp) {
-      with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value, double, true>),
-                           dim3(na), dim3(NT), shm, st, d_chains, tb, rp);
-      });
+      HIPCHK(e);
     } else {
-      with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value,
-                                                         typename decltype(rt)::type>),
-                           dim3(na), dim3(NT), shm, st, d_chains, tb, rp);
-      });
+      const Chain *d_chains = (const Chain *)(dev + ra.o_desc);
+      if (mp) {
+        with_variant(variant_of(h0->p), [&](auto gs, auto pm) {
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value, double, true>),
+                             dim3(na), dim3(NT), shm, st, d_chains, tb, rp);
+        });
+      } else {
+        with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
+          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value,
+                                                           typename decltype(rt)::type>),
+                             dim3(na), dim3(NT), shm, st, d_chains, tb, rp);
+        });
+      }
     }
-    RUNCHK(hipGetLastError());
-    RUNCHK(hipEventRecord(h0->ev1, st));
-    hs.assign(8 * na, 0.0);
-    RUNCHK(hipMemcpyAsync(hs.data(), d_stats, sizeof(double) * 8 * na, hipMemcpyDeviceToHost, st));
-    RUNCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(h0->ev1, st));
+    HIPCHK(hipMemcpyAsync(h_stats, d_stats, sizeof(double) * RUN_NSTAT * na, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     float ms = 0;
-    RUNCHK(hipEventElapsedTime(&ms, h0->ev0, h0->ev1));
+    HIPCHK(hipEventElapsedTime(&ms, h0->ev0, h0->ev1));
     kernel_ms += ms;
     for (int k = 0; k < na; ++k) {
       const int c = ids[k];
-      const double *v = &hs[8 * k];
+      const double *v = &h_stats[RUN_NSTAT * k];
       for (int j = 0; j < 8; ++j)
-        if (j != 4) acc[8 * c + j] += v[j];
+        if (j != 4) acc[RUN_NSTAT * c + j] += v[j];
       done[c] += (int64_t)v[0];
+      energy[c] = v[8];
       if ((int)v[4] != 0) {
-        acc[8 * c + 4] = v[4];
+        acc[RUN_NSTAT * c + 4] = v[4];
         rc = (int)v[4];
       }
     }
@@ -1012,25 +1055,20 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
       }
     }
   }
-#undef RUNCHK
-  release();
   h0->last_ms[0] = kernel_ms;
-  for (int c = 0; c < n_chains; ++c) {
-    double U[2] = {0, 0};
-    if (hipMemcpy(U, chains[c]->ch.U, sizeof(U), hipMemcpyDeviceToHost) != hipSuccess) return FMM_MC_EDEVICE;
-    if (stats) {
-      const double *v = &acc[8 * c];
+  if (stats)
+    for (int c = 0; c < n_chains; ++c) {
+      const double *v = &acc[RUN_NSTAT * c];
       stats[c].proposed = (int64_t)v[0];
       stats[c].accepted = (int64_t)v[1];
       stats[c].singular = (int64_t)v[2];
       stats[c].dE_sum = v[3];
-      stats[c].energy = U[0];
+      stats[c].energy = energy[c];
       stats[c].status = (int32_t)v[4];
       stats[c].t_propose_us = v[5];
       stats[c].t_accept_us = v[6];
       stats[c].t_wait_us = v[7];
     }
-  }
   return rc;
 }
 
@@ -1059,24 +1097,41 @@ int fmm_mc_replay(fmm_mc_t h, int64_t m, const int64_t *idx, const double *new_p
     if (idx[i] < 0 || idx[i] >= h->n) return FMM_MC_ERANGE;
     if (!finite3(new_pos + 3 * i) || !std::isfinite(u[i])) return FMM_MC_EINVAL;
   }
-  double *d_dE = nullptr;
+  // the fixed lists in and the per-step results out, in stream-ordered
+  // device memory of this call (the replay is the test path)
+  double *d_dE = nullptr, *d_lpos = nullptr, *d_lu = nullptr;
+  int64_t *d_lidx = nullptr;
   uint8_t *d_acc = nullptr;
   int32_t *d_leaf = nullptr;
   HIPCHK(hipMallocAsync((void **)&d_dE, sizeof(double) * m, h->stream));
   HIPCHK(hipMallocAsync((void **)&d_acc, m, h->stream));
   HIPCHK(hipMallocAsync((void **)&d_leaf, sizeof(int32_t) * m, h->stream));
+  HIPCHK(hipMallocAsync((void **)&d_lidx, sizeof(int64_t) * m, h->stream));
+  HIPCHK(hipMallocAsync((void **)&d_lpos, sizeof(double) * 3 * m, h->stream));
+  HIPCHK(hipMallocAsync((void **)&d_lu, sizeof(double) * m, h->stream));
+  int rc = FMM_MC_OK;
+  if (hipMemcpyAsync(d_lidx, idx, sizeof(int64_t) * m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipMemcpyAsync(d_lpos, new_pos, sizeof(double) * 3 * m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipMemcpyAsync(d_lu, u, sizeof(double) * m, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    rc = FMM_MC_EDEVICE;
   double zero = 0.0;
   fmm_mc_t hs[1] = {h};
-  int rc = run_chains(hs, 1, m, 0, 0, beta, &zero, 0, 0, idx, new_pos, u, nullptr, nullptr, d_dE, d_acc, d_leaf,
-                      nullptr);
+  if (rc == FMM_MC_OK)
+    rc = run_chains(hs, 1, m, 0, 0, beta, &zero, 0, 0, d_lidx, d_lpos, d_lu, nullptr, nullptr, d_dE, d_acc, d_leaf,
+                    nullptr);
   if (rc == FMM_MC_OK) {
-    if (dE) HIPCHK(hipMemcpyAsync(dE, d_dE, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
-    if (acc) HIPCHK(hipMemcpyAsync(acc, d_acc, m, hipMemcpyDeviceToHost, h->stream));
-    if (leaf) HIPCHK(hipMemcpyAsync(leaf, d_leaf, sizeof(int32_t) * m, hipMemcpyDeviceToHost, h->stream));
+    if (dE && hipMemcpyAsync(dE, d_dE, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+      rc = FMM_MC_EDEVICE;
+    if (acc && hipMemcpyAsync(acc, d_acc, m, hipMemcpyDeviceToHost, h->stream) != hipSuccess) rc = FMM_MC_EDEVICE;
+    if (leaf && hipMemcpyAsync(leaf, d_leaf, sizeof(int32_t) * m, hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+      rc = FMM_MC_EDEVICE;
   }
-  HIPCHK(hipFreeAsync(d_dE, h->stream));
-  HIPCHK(hipFreeAsync(d_acc, h->stream));
-  HIPCHK(hipFreeAsync(d_leaf, h->stream));
+  (void)hipFreeAsync(d_dE, h->stream);
+  (void)hipFreeAsync(d_acc, h->stream);
+  (void)hipFreeAsync(d_leaf, h->stream);
+  (void)hipFreeAsync(d_lidx, h->stream);
+  (void)hipFreeAsync(d_lpos, h->stream);
+  (void)hipFreeAsync(d_lu, h->stream);
   HIPCHK(hipStreamSynchronize(h->stream));
   return rc;
 }
@@ -1295,6 +1350,12 @@ int fmm_mc_set_helpers(fmm_mc_t h, int helpers) {
 
 int fmm_mc_destroy(fmm_mc_t h) {
   if (!h) return FMM_MC_EINVAL;
+  // nothing of this handle may still be in flight when its objects go
+  (void)hipStreamSynchronize(h->stream);
+  if (h->cap_stream) (void)hipStreamSynchronize(h->cap_stream);
+  if (h->run_dev) (void)hipFree(h->run_dev);
+  if (h->run_host) (void)hipHostFree(h->run_host);
+  if (h->host_stats) (void)hipHostFree(h->host_stats);
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);

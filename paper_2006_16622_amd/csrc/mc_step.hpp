@@ -77,6 +77,9 @@ __device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<G
     }
   if (state && threadIdx.x < 3) sm.st[threadIdx.x] = ch.dip[threadIdx.x];
   if (state && threadIdx.x == 3) sm.st[3] = ch.U[0];
+  // the image mask of the first proposal starts empty (each proposal clears
+  // it again after its last barrier)
+  if (threadIdx.x == 0) sm.ints[I_MASK] = 0;
 }
 
 // write the chain's small state back to global memory (all threads)
@@ -180,7 +183,6 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
   // one round of loads; the capacity is at least 32 slots) and used later.
   double dold = 0.0, dnew = 0.0;
   int singular = 0;
-  if (t == 0) ints[I_MASK] = 0;
   const int e = t >> 2, j0 = t & 3;
   const int side = e / 27, ee = e % 27;
   int w = 13, cnt = 0, id = -1, id1 = -1;
@@ -435,7 +437,28 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
   out.dE = dE;
   out.singular = sing;
   __syncthreads();
+  // every read of the image mask is behind the barrier above and every
+  // write of the next proposal behind at least one more: clearing it here
+  // needs no barrier of its own
+  if (t == 0) ints[I_MASK] = 0;
   return out;
+}
+
+// An accepted move of a charge into another leaf cell whose bin is full
+// would overflow the bin (fixed-capacity cell arrays, Sec. 4.1). The run
+// kernels test it at the decision, from the occupancy the proposal read, and
+// stop with FMM_MC_EOVERFLOW before any state changes; the single-call
+// accept tests it from memory.
+__device__ __forceinline__ bool move_overflows(const Chain &ch, const Move &mv, const int *ints) {
+  const int L = ch.L;
+  const bool same = mv.c0[L][0] == mv.c1[L][0] && mv.c0[L][1] == mv.c1[L][1] && mv.c0[L][2] == mv.c1[L][2];
+  return !same && ints[I_CNTNEW] >= ch.B;
+}
+__device__ __forceinline__ bool move_overflows_mem(const Chain &ch, const Move &mv) {
+  const int L = ch.L, n = 1 << (L - 1);
+  const int oldc = lin3(n, mv.c0[L][0], mv.c0[L][1], mv.c0[L][2]);
+  const int newc = lin3(n, mv.c1[L][0], mv.c1[L][1], mv.c1[L][2]);
+  return oldc != newc && glb(ch.bin_cnt)[newc] >= ch.B;
 }
 
 // ------------------------------------------------------------------ accept
@@ -886,6 +909,11 @@ __device__ __forceinline__ int accept_bookkeeping(const Chain &ch, const Tabs &t
     ints[I_FLAG] = ovf;
   }
   __syncthreads();
+  const int ovf = ints[I_FLAG];
+  if (ovf) {  // unreachable after the decision-time test; the state is left as it was
+    __syncthreads();
+    return ovf;
+  }
   if (REUSE) {
     // the proposal of this move left dk in sm.dk and R(dk) in sm.latO; its
     // conj T is the P2M term (the conjugate harmonics are a sign change per
@@ -903,9 +931,7 @@ __device__ __forceinline__ int accept_bookkeeping(const Chain &ch, const Tabs &t
     lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk, [&](int s, double v) { sm.H[s] += v; });
   }
   __syncthreads();
-  int ovf = ints[I_FLAG];
-  __syncthreads();
-  return ovf;
+  return 0;
 }
 
 // the bin records of the bookkeeping, read from global memory (for an

@@ -34,9 +34,11 @@ struct RunParams {
   int64_t steps, t0;
   uint64_t seed;
   double beta;
-  const double *max_step;  // per chain of the run
-  const int64_t *first;    // per slot, null: 0
+  const double *max_step;  // per chain of the run, null: max_step0 for every chain
+  const int64_t *first;    // per slot, null: first0 for every slot
   const int *chain_id;     // per slot, null: the slot
+  double max_step0;
+  int64_t first0;
   int64_t acc_limit;       // 0: none
   // fixed-list source (replay) when list_idx != nullptr
   const int64_t *list_idx;
@@ -47,8 +49,18 @@ struct RunParams {
   double *tr_pos, *tr_dE;
   uint8_t *tr_acc;
   int32_t *tr_leaf;
-  double *stats;           // per chain 8 doubles: proposed, accepted, singular, dE_sum, status, times
+  double *stats;           // per slot RUN_NSTAT doubles: proposed, accepted, singular, dE_sum, status,
+                           // three times, running energy at the end of the launch
 };
+
+constexpr int RUN_NSTAT = 10;
+
+__device__ __forceinline__ double run_max_step(const RunParams &rp, int c) {
+  return rp.max_step ? rp.max_step[c] : rp.max_step0;
+}
+__device__ __forceinline__ int64_t run_first(const RunParams &rp, int slot) {
+  return rp.first ? rp.first[slot] : rp.first0;
+}
 
 // the draw of one step and the record of its particle (LDS)
 struct NextDraw {
@@ -103,18 +115,18 @@ k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
   extern __shared__ double lds[];
   __shared__ Move mv;
   __shared__ NextDraw nd;
-  __shared__ int s_acc;
+  __shared__ int s_acc, s_ovf;
   __shared__ double s_u;
   __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
   const int slot = blockIdx.x, t = threadIdx.x;
   const int c = rp.chain_id ? rp.chain_id[slot] : slot;
-  const int64_t s0 = rp.first ? rp.first[slot] : 0;
+  const int64_t s0 = run_first(rp, slot);
   if (t == 0) chl = chains[slot];
   __syncthreads();
   const Chain &ch = chl;
   Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
-  const double D = rp.max_step[c];
+  const double D = run_max_step(rp, c);
   double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
   uint64_t tick_prop = 0, tick_acc = 0;
   int status = 0;
@@ -146,6 +158,10 @@ k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
     tick_prop += t_1 - t_0;
     if (t == 0) {
       int acc = !po.singular && (u < exp(-rp.beta * po.dE));
+      // a move that would overflow its new leaf bin is not taken: the chain
+      // stops with the error and its state is that before the move
+      s_ovf = acc && move_overflows(ch, mv, sm.ints);
+      if (s_ovf) acc = 0;
       s_acc = acc;
       nprop += 1;
       nsing += po.singular;
@@ -162,6 +178,10 @@ k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
     }
     __syncthreads();
     prev_acc = s_acc;
+    if (s_ovf) {
+      status = -7;
+      break;
+    }
     prev_idx = mv.idx;
     for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
     if (prev_acc) {
@@ -185,7 +205,7 @@ k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
   __syncthreads();
   writeback_lds(ch, tb, sm);
   if (t == 0) {
-    double *st = rp.stats + 8 * slot;
+    const auto st = glb(rp.stats) + RUN_NSTAT * slot;
     st[0] = nprop;
     st[1] = nacc;
     st[2] = nsing;
@@ -194,6 +214,7 @@ k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
     st[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
     st[6] = tick_acc * 0.01;
     st[7] = 0.0;
+    st[8] = sm.st[3];
   }
 }
 
@@ -358,7 +379,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   extern __shared__ double lds[];
   __shared__ Move mv;
   __shared__ NextDraw nd;
-  __shared__ int s_flag, s_acc;
+  __shared__ int s_flag, s_acc, s_ovf;
   __shared__ unsigned s_seq;
   __shared__ double s_u;
   __shared__ uint64_t s_ticks;
@@ -376,7 +397,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   __syncthreads();
   if (w == 0) {
     const int c = rp.chain_id ? rp.chain_id[0] : 0;
-    const double D = rp.max_step[c];
+    const double D = run_max_step(rp, c);
     double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
     int status = 0;
     unsigned num = 0;  // move number of this launch
@@ -384,7 +405,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     bool prev_acc = false;
     int prev_idx = -1;
     double prev_rn[3] = {0, 0, 0};
-    const int64_t s0 = rp.first ? rp.first[0] : 0;
+    const int64_t s0 = run_first(rp, 0);
     int64_t acc_launch = 0;
     // the rows of the last accepted move may still be in flight (helpers
     // finish them while the next proposal forms its other terms)
@@ -428,6 +449,10 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       }
       if (t == 0) {
         int acc = !po.singular && (u < exp(-rp.beta * po.dE));
+        // a move that would overflow its new leaf bin is published as
+        // rejected (the helpers drop its rows) and the chain stops
+        s_ovf = acc && move_overflows(ch, mv, sm.ints);
+        if (s_ovf) acc = 0;
         s_acc = acc;
         nprop += 1;
         nsing += po.singular;
@@ -449,6 +474,10 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
           int n = 1 << (ch.L - 1);
           glb(rp.tr_leaf)[o] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
         }
+      }
+      if (s_ovf) {
+        status = -7;
+        break;
       }
       prev_idx = mv.idx;
       for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
@@ -491,6 +520,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       glb(rp.stats)[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
       glb(rp.stats)[6] = tick_acc * 0.01;
       glb(rp.stats)[7] = tick_wait * 0.01;
+      glb(rp.stats)[8] = sm.st[3];
     }
     return;
   }
@@ -651,7 +681,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
   extern __shared__ double lds[];
   __shared__ Move mvs[2];  // the move of this step and the next (workgroup 0); helpers use mvs[0]
   __shared__ NextDraw nd;
-  __shared__ int s_flag, s_acc;
+  __shared__ int s_flag, s_acc, s_ovf;
   __shared__ unsigned s_seq;
   __shared__ double s_u, s_far;
   __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
@@ -667,12 +697,12 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
   __syncthreads();
   if (w == 0) {
     const int c = rp.chain_id ? rp.chain_id[0] : 0;
-    const double D = rp.max_step[c];
+    const double D = run_max_step(rp, c);
     double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
     int status = 0;
     unsigned num = 0;  // move number of this launch
     uint64_t tick_prop = 0, tick_acc = 0, tick_wait = 0;
-    const int64_t s0 = rp.first ? rp.first[0] : 0;
+    const int64_t s0 = run_first(rp, 0);
     int64_t acc_launch = 0;
     int cur = 0;  // mvs[cur]: the move of this step, located and posted
     // the move of step s0 (no move accepted before it in this launch)
@@ -749,6 +779,8 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
       tick_wait += t_1 - t_w;
       if (t == 0) {
         int acc = !po.singular && (u < exp(-rp.beta * dE));
+        s_ovf = acc && move_overflows(ch, mv, sm.ints);
+        if (s_ovf) acc = 0;
         s_acc = acc;
         nprop += 1;
         nsing += po.singular;
@@ -765,6 +797,10 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
       }
       __syncthreads();
       const bool acc = s_acc;
+      if (s_ovf) {
+        status = -7;
+        break;
+      }
       const bool last = acc && rp.acc_limit && acc_launch + 1 >= rp.acc_limit;
       if (acc) {
         // the multipoles first: the next move may be posted only when every
@@ -810,6 +846,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
       glb(rp.stats)[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
       glb(rp.stats)[6] = tick_acc * 0.01;
       glb(rp.stats)[7] = tick_wait * 0.01;
+      glb(rp.stats)[8] = sm.st[3];
     }
     return;
   }
@@ -918,6 +955,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_accept_blocks(Chain ch, Tabs tb, 
   Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, false);
   move_direct(ch, idx, x, y, z, mv);
+  if (move_overflows_mem(ch, mv)) return;  // uniform over the workgroup
   accept_block<GS, PM, R>(ch, tb, mv, blockIdx.x, sm);
 }
 
@@ -932,12 +970,18 @@ __global__ void __launch_bounds__(WG_SINGLE) k_accept_book(Chain ch, Tabs tb, in
   Lds<GS, NT> sm(lds, tb.Cs, tb.lat_lds ? tb.lat_w : 0);
   stage_lds(ch, tb, sm, true);
   move_direct(ch, idx, x, y, z, mv);
+  // status word 0 of the single-call accept: FMM_MC_EOVERFLOW, with the
+  // state unchanged, when the move would overflow its new leaf bin
+  if (move_overflows_mem(ch, mv)) {
+    if (threadIdx.x == 0) glb(ch.status)[0] = -7;
+    return;
+  }
   if constexpr (MP) accept_mp_wg<GS, PM, NT>(ch, tb, mv, sm.rec);
   load_bin_records(ch, mv, sm);
   __syncthreads();
   int ovf = accept_bookkeeping<GS, PM>(ch, tb, mv, dE, sm);
   writeback_lds(ch, tb, sm);
-  if (threadIdx.x == 0 && ovf) glb(ch.status)[0] = -7;
+  if (threadIdx.x == 0) glb(ch.status)[0] = ovf ? -7 : 0;
 }
 
 }  // namespace fmmdev

@@ -106,6 +106,8 @@ def test_rocksalt_proposals_p12(rocksalt_ewald):
     err_o = rel_rms(de_o, ref[:k])
     say(f"[accuracy] oracle on the first {k}: relative RMS error {err_o:.3e}")
     assert err < 5e-4 and dp < 1e-3
+    # the oracle itself carries the same truncation: the GPU adds nothing
+    assert err_o < 5e-4 and rel_rms(de[:k], ref[:k]) == pytest.approx(err_o, rel=1e-6)
 
 
 def test_rocksalt_proposals_p20_meet_gate(rocksalt_ewald):

@@ -126,12 +126,32 @@ def test_leaf_overflow_is_reported():
     g = np.random.default_rng(98)
     count = int(in_leaf.sum())
     code = 0
+    orc = O.Multilevel(wl.pos, wl.q, wl.box, wl.depth, wl.p)
+    before = None
     for k in movers:
         target = g.uniform(0.01, 0.24, 3)
+        before = (gpu.positions(), gpu.running_energy(), gpu.locals(2), gpu.locals(3), gpu.energy())
         try:
             gpu.accept(k, target)
         except FmmMcError as e:
             code = e.code
             break
+        orc.accept(k, target)
         count += 1
     assert code == EOVERFLOW and count == cap
+    # the refused move changed nothing: positions, running energy, every
+    # expansion and the energy are those before it, and the chain goes on
+    # exactly as the oracle that never saw the move
+    assert np.array_equal(gpu.positions(), before[0])
+    assert gpu.running_energy() == before[1]
+    assert np.array_equal(gpu.locals(2), before[2]) and np.array_equal(gpu.locals(3), before[3])
+    assert gpu.energy() == before[4]
+    assert np.array_equal(gpu.positions(), orc.positions())
+    # a charge inside the full leaf moves within it (no change of bin)
+    cur = gpu.positions()
+    k = int(np.nonzero(((cur >= 0.03) & (cur < 0.22)).all(axis=1))[0][0])
+    rn = cur[k] + np.array([0.01, -0.02, 0.015])
+    assert gpu.propose(k, rn) == pytest.approx(orc.propose(k, rn), rel=1e-10, abs=1e-10)
+    gpu.accept(k, rn)
+    orc.accept(k, rn)
+    assert np.array_equal(gpu.positions(), orc.positions())

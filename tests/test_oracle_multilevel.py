@@ -127,3 +127,57 @@ def test_run_decisions_follow_metropolis_rule():
         i, d, u = O.draw(wl.seed, 0, t, wl.n, wl.max_step)
         assert i == tr["idx"][t] and u == tr["u"][t]
     assert 0 < tr["acc"].sum() < 60
+
+
+def _deep_moves(pos, count, step, seed):
+    g = np.random.default_rng(seed)
+    ks = g.integers(0, len(pos), count)
+    return [(int(k), pos[k] + g.uniform(-step, step, 3)) for k in ks]
+
+
+@pytest.mark.parametrize("depth,n,bound12,bound8", [(3, 2000, 1e-5, 3e-4), (4, 4000, 2e-5, 1e-3)])
+def test_deep_periodic_dE_converges_to_ewald(depth, n, bound12, bound8):
+    # Depth >= 3 under periodicity: levels with 4 and more cells per side,
+    # where interaction lists are no longer aliased and the images of the
+    # extended domain enter through distinct cells. The error against Ewald
+    # must be small at p = 12 and fall by more than an order of magnitude
+    # from p = 8 (a wrong offset, sign or missing level would not converge).
+    pos, q = _system(n, 40 + depth)
+    mv = _deep_moves(pos, 30, 0.3 / n ** (1 / 3), 7)
+    e = O.Ewald(pos, q, 1.0)
+    ref = np.array([e.propose(k, r) for k, r in mv])
+    err = {}
+    for p in (8, 12):
+        m = O.Multilevel(pos, q, 1.0, depth, p, setup="lazy")
+        de = np.array([m.propose(k, r) for k, r in mv])
+        err[p] = np.sqrt(np.mean((de - ref) ** 2)) / np.sqrt(np.mean(ref ** 2))
+    assert err[12] < bound12 and err[8] < bound8
+    assert err[8] > 10 * err[12]
+
+
+def test_deep_periodic_accepts_follow_ewald():
+    # depth 3, p = 12: 20 accepted moves (Alg. L.2 on levels 2..4 with
+    # images), then proposals from the moved state against Ewald following
+    # the same accepts
+    pos, q = _system(2000, 43)
+    m = O.Multilevel(pos, q, 1.0, 3, 12, setup="lazy")
+    e = O.Ewald(pos, q, 1.0)
+    step = 0.3 / 2000 ** (1 / 3)
+    for k, r in _deep_moves(pos, 20, step, 11):
+        m.accept(k, r)
+        e.accept(k, r)
+    cur = m.positions()
+    assert np.allclose(cur, e_positions_after(pos, _deep_moves(pos, 20, step, 11)), rtol=0, atol=0)
+    mv = _deep_moves(cur, 30, step, 12)
+    de = np.array([m.propose(k, r) for k, r in mv])
+    ref = np.array([e.propose(k, r) for k, r in mv])
+    assert np.sqrt(np.mean((de - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)) < 1e-5
+
+
+def e_positions_after(pos, moves):
+    """positions after the moves, wrapped into the unit box (no arithmetic
+    of the method: the wrap of the oracle itself)"""
+    out = pos.copy()
+    for k, r in moves:
+        out[k] = [O.wrap(float(v), 1.0) for v in r]
+    return out
