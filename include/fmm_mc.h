@@ -179,6 +179,27 @@ typedef struct {
 int fmm_mc_run(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t seed,
                const fmm_mc_run_opts *opts, fmm_mc_stats *stats);
 
+/* Most chains one fmm_mc_run_noalloc call takes. */
+#define FMM_MC_NOALLOC_MAX_CHAINS 1024
+
+/* fmm_mc_run for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation. Same
+ * arguments, semantics and results as fmm_mc_run, bit for bit. It calls no
+ * hipMalloc, hipFree or other allocating routine: the launch arguments and
+ * per-chain results of a run of several chains (which fmm_mc_run keeps in
+ * buffers it allocates on first use) live in a fixed device array of 1 MiB
+ * that each GPU the library runs on holds until the process ends, and in a
+ * host staging block allocated once by the first fmm_mc_setup of the
+ * process; a run of one chain on the whole GPU uses only its workspace, as
+ * in fmm_mc_run. Limits: n_chains <= FMM_MC_NOALLOC_MAX_CHAINS (more:
+ * FMM_MC_ENOMEM, before anything is touched); opts->resetup_every must be 0
+ * (a re-setup builds its graph on first use; FMM_MC_EINVAL otherwise).
+ * Every call on one GPU shares that GPU's array (every call writes all of
+ * the part it reads): calls that overlap on one GPU race, and calls from
+ * several host threads are serialised by a lock. */
+int fmm_mc_run_noalloc(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t seed,
+                       const fmm_mc_run_opts *opts, fmm_mc_stats *stats);
+
 /* Fixed-list mode: m proposals (idx[m], new_pos[m x 3], uniforms u[m], all
  * host) applied in order with the rule u < exp(-beta dE). Outputs (host,
  * may be NULL): dE[m], acc[m] (0/1), leaf[m] = leaf cell of the wrapped

@@ -73,6 +73,8 @@ SYMBOLS = {
     "fmm_mc_accept": (ctypes.c_int, [_vp, ctypes.c_int64, _dp, _dp, _dp]),
     "fmm_mc_run": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
                                   ctypes.POINTER(RunOpts), ctypes.POINTER(Stats)]),
+    "fmm_mc_run_noalloc": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                                          ctypes.POINTER(RunOpts), ctypes.POINTER(Stats)]),
     "fmm_mc_replay": (ctypes.c_int, [_vp, ctypes.c_int64, _i64p, _dp, _dp, ctypes.c_double, _dp, _u8p, _i32p]),
     "fmm_mc_energy": (ctypes.c_int, [_vp, _dp]),
     "fmm_mc_running_energy": (ctypes.c_int, [_vp, _dp]),
@@ -291,12 +293,13 @@ def setup_batch(systems, p: int, flags: int = 0, device: str = "cuda:0", stream=
 
 
 def run_chains(chains, steps: int, seed: int, beta: float, max_step, t0: int = 0, mode: int = 0,
-               traces: bool = False, resetup_every: int = 0, trace_ptrs=None):
+               traces: bool = False, resetup_every: int = 0, trace_ptrs=None, noalloc: bool = False):
     """fmm_mc_run over a list of Chain objects (same device and stream).
     With traces, device buffers (torch) are allocated and returned as numpy.
     trace_ptrs: device addresses (ints) of caller-owned trace buffers,
     keys idx, newpos, dE, acc, laid out [chain * steps + t] as in
-    fmm_mc_run_opts; nothing is allocated or returned for them."""
+    fmm_mc_run_opts; nothing is allocated or returned for them.
+    noalloc: call fmm_mc_run_noalloc instead of fmm_mc_run."""
     import torch
     lib = load_library()
     nc = len(chains)
@@ -326,8 +329,9 @@ def run_chains(chains, steps: int, seed: int, beta: float, max_step, t0: int = 0
         opts.trace_dE = tr["dE"].data_ptr()
         opts.trace_acc = tr["acc"].data_ptr()
     stats = (Stats * nc)()
-    rc = lib.fmm_mc_run(hs, nc, int(steps), int(seed), ctypes.byref(opts), stats)
-    _check(rc, "fmm_mc_run")
+    entry = lib.fmm_mc_run_noalloc if noalloc else lib.fmm_mc_run
+    rc = entry(hs, nc, int(steps), int(seed), ctypes.byref(opts), stats)
+    _check(rc, "fmm_mc_run_noalloc" if noalloc else "fmm_mc_run")
     out = [dict(proposed=s.proposed, accepted=s.accepted, singular=s.singular, dE_sum=s.dE_sum,
                 energy=s.energy, status=s.status, t_propose_us=s.t_propose_us,
                 t_accept_us=s.t_accept_us, t_wait_us=s.t_wait_us) for s in stats]

@@ -480,6 +480,67 @@ bool in_box(const double *v, double a) {
 
 }  // namespace
 
+// Device and pinned host buffers of a run of many chains (one workgroup
+// each), kept by the handle of the run's first chain: the chain
+// descriptors, first steps and ids of a launch's slots, the step sizes of
+// the run's chains and the per-slot results. Allocated on the first such
+// run and grown only when a run has more chains than any before, so that
+// repeated runs allocate nothing.
+static constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+static constexpr size_t run_area_bytes(size_t n_chains) {
+  return round256(sizeof(Chain) * n_chains) + round256(sizeof(int64_t) * n_chains) +
+         round256(sizeof(int) * n_chains) + round256(sizeof(double) * n_chains) +
+         round256(sizeof(double) * RUN_NSTAT * n_chains);
+}
+struct RunArea {
+  size_t o_desc, o_first, o_id, o_step, o_stats, bytes;
+  RunArea(int n_chains) {
+    o_desc = 0;
+    o_first = o_desc + round256(sizeof(Chain) * n_chains);
+    o_id = o_first + round256(sizeof(int64_t) * n_chains);
+    o_step = o_id + round256(sizeof(int) * n_chains);
+    o_stats = o_step + round256(sizeof(double) * n_chains);
+    bytes = o_stats + round256(sizeof(double) * RUN_NSTAT * n_chains);
+  }
+};
+
+// ---- fixed memory of fmm_mc_run_noalloc (callers that cannot allocate).
+// The argument and result block of a run of many chains lives in this
+// array instead of the first handle's buffers. Each GPU holds its own copy
+// of it for the life of the process; its address on a device is looked up
+// once, at the first setup on that device, and only that address is used
+// from the host. Every call on one GPU uses the same array (and the same
+// host staging, under a lock), so calls that overlap on one GPU race.
+static constexpr size_t NOALLOC_SCRATCH_BYTES = 1u << 20;
+static_assert(run_area_bytes(FMM_MC_NOALLOC_MAX_CHAINS) <= NOALLOC_SCRATCH_BYTES, "scratch too small");
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+// host side: the device address of `scratch` per device, and one pinned
+// staging block of the same layout plus the run's host bookkeeping
+// (allocated at the first setup in the process, under g_mu)
+static constexpr int MAX_DEVICES = 64;
+static void *g_scratch_dev[MAX_DEVICES] = {};
+static std::mutex g_noalloc_mu;  // held for the whole of a fmm_mc_run_noalloc call
+static char *g_noalloc_host = nullptr;
+static constexpr size_t noalloc_work_bytes(size_t n) {
+  return sizeof(int64_t) * n + sizeof(double) * RUN_NSTAT * n + sizeof(double) * n + sizeof(int) * n;
+}
+static constexpr size_t NOALLOC_HOST_BYTES = NOALLOC_SCRATCH_BYTES + noalloc_work_bytes(FMM_MC_NOALLOC_MAX_CHAINS);
+
+// at setup, with the chain's device current: look up the address of
+// `scratch` on it, and allocate the host staging once per process.
+// Failures are left for fmm_mc_run_noalloc to report.
+static void noalloc_prepare(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_dev[dev] = ptr;
+  }
+  if (!g_noalloc_host && hipHostMalloc((void **)&g_noalloc_host, NOALLOC_HOST_BYTES, hipHostMallocDefault) != hipSuccess)
+    g_noalloc_host = nullptr;
+}
+
 extern "C" {
 
 int fmm_mc_workspace_bytes(int64_t n, int levels, int p, uint32_t flags, size_t *bytes) {
@@ -529,6 +590,7 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
     delete h;
     return FMM_MC_EDEVICE;
   }
+  noalloc_prepare(h->device);
   h->stream = (hipStream_t)hip_stream;
   h->n = n;
   h->levels = levels;
@@ -807,30 +869,6 @@ int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *
   return status ? status : FMM_MC_OK;
 }
 
-// Device and pinned host buffers of a run of many chains (one workgroup
-// each), kept by the handle of the run's first chain: the chain
-// descriptors, first steps and ids of a launch's slots, the step sizes of
-// the run's chains and the per-slot results. Allocated on the first such
-// run and grown only when a run has more chains than any before, so that
-// repeated runs allocate nothing.
-struct RunArea {
-  size_t o_desc, o_first, o_id, o_step, o_stats, bytes;
-  RunArea(int n_chains) {
-    size_t o = 0;
-    auto take = [&](size_t b) {
-      size_t r = o;
-      o += (b + 255) / 256 * 256;
-      return r;
-    };
-    o_desc = take(sizeof(Chain) * n_chains);
-    o_first = take(sizeof(int64_t) * n_chains);
-    o_id = take(sizeof(int) * n_chains);
-    o_step = take(sizeof(double) * n_chains);
-    o_stats = take(sizeof(double) * RUN_NSTAT * n_chains);
-    bytes = o;
-  }
-};
-
 static int ensure_run_area(fmm_mc_ctx *h, size_t bytes) {
   if (h->run_dev_cap < bytes) {
     if (h->run_dev) {
@@ -859,7 +897,8 @@ static int ensure_run_area(fmm_mc_ctx *h, size_t bytes) {
 // is the first chain's buffers above; fmm_mc_run_noalloc hands in its own.
 struct RunMem {
   char *dev = nullptr;   // device block laid out as RunArea
-  char *host = nullptr;  // host staging of the same layout (pinned or not)
+  char *host = nullptr;  // host staging of the same layout
+  char *work = nullptr;  // noalloc_work_bytes(n_chains) of host bookkeeping
 };
 
 // shared driver of fmm_mc_run, fmm_mc_run_noalloc and fmm_mc_replay. With
@@ -903,7 +942,7 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
     }
   }
   double *d_stats = single ? (double *)(h0->ws + h0->ly.off[O_STATS]) : (double *)(dev + ra.o_stats);
-  double *h_stats = single ? (mem ? (double *)mem->host : h0->host_stats) : (double *)(host + ra.o_stats);
+  double *h_stats = single ? h0->host_stats : (double *)(host + ra.o_stats);
   RunParams rp{};
   rp.steps = steps;
   rp.t0 = t0;
@@ -923,7 +962,8 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   rp.tr_acc = tr_acc;
   rp.tr_leaf = tr_leaf;
   rp.stats = d_stats;
-  if (!single) std::memcpy(host + ra.o_step, steps_h, sizeof(double) * n_chains);
+  if (!single && steps_h != (const double *)(host + ra.o_step))
+    std::memcpy(host + ra.o_step, steps_h, sizeof(double) * n_chains);
   int G = 1;
   if (single && mp) {
     // workgroup 0 proposes and accepts, the others (one per CU at most)
@@ -965,19 +1005,25 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
     HIPCHK(oe);
     if (per < 1) return FMM_MC_EDEVICE;
   }
-  // per chain of the run: steps done, accumulated counters, final energy
-  std::vector<int64_t> done(n_chains, 0);
-  std::vector<double> acc(RUN_NSTAT * n_chains, 0.0);
-  std::vector<double> energy(n_chains, 0.0);
-  std::vector<int> ids;
-  ids.reserve(n_chains);
+  // per chain of the run: steps done, accumulated counters, final energy,
+  // and the chains of a launch's slots
+  std::vector<char> own;
+  char *work = mem ? mem->work : nullptr;
+  if (!work) {
+    own.resize(noalloc_work_bytes(n_chains));
+    work = own.data();
+  }
+  int64_t *done = (int64_t *)work;
+  double *acc = (double *)(done + n_chains);
+  double *energy = acc + RUN_NSTAT * n_chains;
+  int *ids = (int *)(energy + n_chains);
+  std::memset(work, 0, noalloc_work_bytes(n_chains));
   double kernel_ms = 0.0;
   int rc = FMM_MC_OK;
   while (rc == FMM_MC_OK) {
-    ids.clear();
+    int na = 0;
     for (int c = 0; c < n_chains; ++c)
-      if (done[c] < steps) ids.push_back(c);
-    const int na = (int)ids.size();
+      if (done[c] < steps) ids[na++] = c;
     if (na == 0) break;
     if (single) {
       rp.first0 = done[0];
@@ -1086,6 +1132,38 @@ int fmm_mc_run(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t seed, con
   return run_chains(chains, n_chains, steps, seed, opts->t0, opts->beta, st.data(), opts->mode, opts->resetup_every,
                     nullptr, nullptr, nullptr, opts->trace_idx, opts->trace_newpos, opts->trace_dE, opts->trace_acc,
                     nullptr, stats);
+}
+
+int fmm_mc_run_noalloc(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t seed, const fmm_mc_run_opts *opts,
+                       fmm_mc_stats *stats) {
+  if (n_chains > FMM_MC_NOALLOC_MAX_CHAINS) return FMM_MC_ENOMEM;
+  if (!chains || n_chains < 1 || steps < 0 || !opts) return FMM_MC_EINVAL;
+  if (!(opts->beta >= 0.0) || !std::isfinite(opts->beta)) return FMM_MC_EINVAL;
+  // a re-setup captures and instantiates a graph on its first use
+  if (opts->resetup_every != 0) return FMM_MC_EINVAL;
+  if (!chains[0] || !chains[0]->ready) return FMM_MC_ESTATE;
+  const int dev = chains[0]->device;
+  if (dev < 0 || dev >= MAX_DEVICES) return FMM_MC_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  RunMem mem;
+  {
+    std::lock_guard<std::mutex> lk2(g_mu);
+    mem.dev = (char *)g_scratch_dev[dev];
+  }
+  mem.host = g_noalloc_host;
+  if (!mem.dev || !mem.host) return FMM_MC_EDEVICE;
+  mem.work = mem.host + NOALLOC_SCRATCH_BYTES;
+  // the step sizes go straight to their place in the staging block
+  const RunArea ra(n_chains);
+  double *st = (double *)(mem.host + ra.o_step);
+  for (int c = 0; c < n_chains; ++c) {
+    st[c] = opts->chain_max_step ? opts->chain_max_step[c] : opts->max_step;
+    if (!(st[c] >= 0.0) || !std::isfinite(st[c])) return FMM_MC_EINVAL;
+  }
+  if (steps == 0) return FMM_MC_OK;
+  return run_chains(chains, n_chains, steps, seed, opts->t0, opts->beta, st, opts->mode, 0, nullptr, nullptr,
+                    nullptr, opts->trace_idx, opts->trace_newpos, opts->trace_dE, opts->trace_acc, nullptr, stats,
+                    &mem);
 }
 
 int fmm_mc_replay(fmm_mc_t h, int64_t m, const int64_t *idx, const double *new_pos, const double *u, double beta,
