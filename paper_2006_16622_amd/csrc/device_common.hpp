@@ -193,13 +193,13 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
   }
 }
 
-// (idx, delta, u) of Metropolis-Hastings step `step` of chain `chain`
-__device__ __forceinline__ void mh_draw(uint64_t seed, uint64_t chain, uint64_t step, int64_t N,
-                                        double D, int64_t &idx, double delta[3], double &u) {
+// the two halves of the draw of Metropolis-Hastings step `step` of chain
+// `chain`: counter (step, 0) gives idx and delta, counter (step, 1) gives u
+__device__ __forceinline__ void mh_draw_move(uint64_t seed, uint64_t chain, uint64_t step, int64_t N, double D,
+                                             int64_t &idx, double delta[3]) {
 #pragma clang fp contract(off)
-  uint64_t w[4] = {step, 0, 0, 0}, v[4] = {step, 1, 0, 0};
+  uint64_t w[4] = {step, 0, 0, 0};
   philox4x64_10(w, seed, chain);
-  philox4x64_10(v, seed, chain);
   idx = (int64_t)__umul64hi(w[0], (uint64_t)N);
   const double two53 = 1.0 / 9007199254740992.0;
 #pragma unroll
@@ -209,7 +209,19 @@ __device__ __forceinline__ void mh_draw(uint64_t seed, uint64_t chain, uint64_t 
     double centred = two_f - 1.0;
     delta[k] = D * centred;
   }
+}
+__device__ __forceinline__ void mh_draw_u(uint64_t seed, uint64_t chain, uint64_t step, double &u) {
+  uint64_t v[4] = {step, 1, 0, 0};
+  philox4x64_10(v, seed, chain);
+  const double two53 = 1.0 / 9007199254740992.0;
   u = (double)(v[0] >> 11) * two53;
+}
+
+// (idx, delta, u) of Metropolis-Hastings step `step` of chain `chain`
+__device__ __forceinline__ void mh_draw(uint64_t seed, uint64_t chain, uint64_t step, int64_t N,
+                                        double D, int64_t &idx, double delta[3], double &u) {
+  mh_draw_move(seed, chain, step, N, D, idx, delta);
+  mh_draw_u(seed, chain, step, u);
 }
 
 // ------------------------------------------------------------------ harmonics
@@ -399,8 +411,8 @@ __device__ __forceinline__ void group_harmonics_sum(int lane, const Tabs &tb, co
 }
 
 // write (or add, with ACC) a group's column sums into the real-layout buffer
-template <int PMAX, bool ACC>
-__device__ __forceinline__ void flush_cols(int lane, const Tabs &tb, const ColSum<PMAX> &acc, double *buf) {
+template <int PMAX, bool ACC, typename P>
+__device__ __forceinline__ void flush_cols(int lane, const Tabs &tb, const ColSum<PMAX> &acc, P buf) {
   const int p = tb.p, m = lane;
   if (m > p) return;
 #pragma unroll
@@ -468,11 +480,39 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
   return r;
 }
 
+// widest ELL row of the lattice operator for the degrees a kernel variant
+// serves (the tables are padded to it with zero entries)
+__host__ __device__ constexpr int ell_width(int pm) { return pm <= 8 ? 10 : pm <= 12 ? 21 : pm <= 15 ? 36 : 78; }
+
+// y[s] = sum_k R[s][k] x[k] over the padded ELL layout, width W known at
+// compile time, so that all of a row's loads are issued before its sums;
+// the even and odd entries are summed apart and then added, the order of
+// lattice_rows below (padding entries add +0)
+template <int NT, int W, typename PV, typename PC, typename F>
+__device__ __forceinline__ void lattice_rows_w(const Tabs &tb, PV val, PC col, const double *x, F &&use) {
+  for (int s = threadIdx.x; s < tb.C; s += NT) {
+    double a[W];
+    int c[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      a[w] = val[(size_t)w * tb.Cs + s];
+      c[w] = col[(size_t)w * tb.Cs + s];
+    }
+    double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+    for (int w = 0; w + 1 < W; w += 2) {
+      v0 += a[w] * x[c[w]];
+      v1 += a[w + 1] * x[c[w + 1]];
+    }
+    if (W % 2) v0 += a[W - 1] * x[c[W - 1]];
+    use(s, v0 + v1);
+  }
+}
+
 // y[s] = sum_k R[s][k] x[k] over the ELL layout of the lattice operator for
 // the output slots s = t, t + NT, ... of the calling thread, handed to `use`
-template <int NT, typename F>
-__device__ __forceinline__ void lattice_rows(const Tabs &tb, const double *val, const int *col,
-                                             const double *x, F &&use) {
+template <int NT, typename PV, typename PC, typename F>
+__device__ __forceinline__ void lattice_rows(const Tabs &tb, PV val, PC col, const double *x, F &&use) {
   for (int s = threadIdx.x; s < tb.C; s += NT) {
     double v0 = 0.0, v1 = 0.0;
     int w = 0;

@@ -154,13 +154,17 @@ int build_tables(int p, DevTables **out) {
   }
   std::vector<double> lat((size_t)C * C);
   fmmhost::lattice_operator(p, lat.data());
-  // ELL layout (column-major by row) of the sparse lattice operator
+  // ELL layout (column-major by row) of the sparse lattice operator, padded
+  // with zero entries (column 0) to the width the kernel variant unrolls
   int W = 1;
   for (int j = 0; j < C; ++j) {
     int nz = 0;
     for (int s = 0; s < C; ++s) nz += lat[(size_t)j * C + s] != 0.0;
     W = std::max(W, nz);
   }
+  // (the variants with groups of 16 lanes, whose whole-GPU proposal unrolls it)
+  const int pmv[3] = {8, 12, 15};
+  if (variant_of(p) < 3) W = std::max(W, ell_width(pmv[variant_of(p)]));
   std::vector<int> ecol((size_t)W * Cs, 0);
   std::vector<double> eval((size_t)W * Cs, 0.0);
   for (int j = 0; j < C; ++j) {
@@ -989,6 +993,15 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
     int ncu = 0, maxlds = 0, per = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h0->device));
     HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, h0->device));
+    // the kernel's own (static) LDS comes out of the same budget
+    hipFuncAttributes fa{};
+    hipError_t ae = hipSuccess;
+    with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
+      ae = hipFuncGetAttributes(
+          &fa, (const void *)k_run_single<decltype(gs)::value, decltype(pm)::value, typename decltype(rt)::type>);
+    });
+    HIPCHK(ae);
+    maxlds -= (int)fa.sharedSizeBytes;
     auto kmax_of = [&](int g) { return g < 2 ? 1 : (nblk + g - 2) / (g - 1); };
     auto shm_of = [&](int g) { return smem_bytes(GS, tb, NT) + (g < 2 ? 0 : spec_extra_bytes(kmax_of(g), NG, h0->Cs)); };
     G = nblk + 1;
@@ -1089,6 +1102,8 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
       if ((int)v[4] != 0) {
         acc[RUN_NSTAT * c + 4] = v[4];
         rc = (int)v[4];
+      } else if (v[0] < 1.0) {
+        rc = FMM_MC_ESTATE;  // a launch that made no step would be relaunched for ever
       }
     }
     if (rc != FMM_MC_OK) break;

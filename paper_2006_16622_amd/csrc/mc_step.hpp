@@ -14,6 +14,7 @@ struct Move {
   int idx;
   double q;
   double r[3], rn[3];   // old and new (wrapped) positions
+  double u;             // uniform of the decision (whole-GPU run)
   int c0[MAXL + 1][3];  // cell of r on each level
   int c1[MAXL + 1][3];  // cell of rn on each level
 };
@@ -26,9 +27,8 @@ __device__ __forceinline__ int ifloordiv(int i, int n) { return (i - imod(i, n))
 __device__ __forceinline__ int pmod(int i, int n) { return i & (n - 1); }
 __device__ __forceinline__ int pfloordiv(int i, int n) { return i >> __builtin_ctz((unsigned)n); }
 
-// cells of r and rn on every level, one level per thread (caller syncs)
-__device__ __forceinline__ void locate_move_par(const Chain &ch, Move &mv) {
-  const int l = threadIdx.x + 1;
+// cells of r and rn on level l (1..L)
+__device__ __forceinline__ void locate_move_level(const Chain &ch, Move &mv, int l) {
   if (l <= ch.L) {
     int n = 1 << (l - 1);
     for (int k = 0; k < 3; ++k) {
@@ -36,6 +36,11 @@ __device__ __forceinline__ void locate_move_par(const Chain &ch, Move &mv) {
       mv.c1[l][k] = cell_coord(mv.rn[k], ch.inv_h[l], n);
     }
   }
+}
+
+// cells of r and rn on every level, one level per thread (caller syncs)
+__device__ __forceinline__ void locate_move_par(const Chain &ch, Move &mv) {
+  locate_move_level(ch, mv, threadIdx.x + 1);
 }
 
 // indices into Lds::ints
@@ -48,6 +53,7 @@ enum : int {
   I_CNTNEW = 111,  // occupancy of the new leaf bin
   I_IDLAST = 112,  // particle in the last slot of the old leaf bin
   I_FLAG = 113,
+  I_SING = 114,    // a new-side near-field distance was zero (propose_fast)
   I_LIST = 128     // candidate list of a coarse accept block (55 entries)
 };
 
@@ -79,7 +85,10 @@ __device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<G
   if (state && threadIdx.x == 3) sm.st[3] = ch.U[0];
   // the image mask of the first proposal starts empty (each proposal clears
   // it again after its last barrier)
-  if (threadIdx.x == 0) sm.ints[I_MASK] = 0;
+  if (threadIdx.x == 0) {
+    sm.ints[I_MASK] = 0;
+    sm.ints[I_SING] = 0;
+  }
 }
 
 // write the chain's small state back to global memory (all threads)
@@ -93,13 +102,16 @@ __device__ __forceinline__ void writeback_lds(const Chain &ch, const Tabs &tb, L
   if (threadIdx.x == 3) ch.U[0] = sm.st[3];
 }
 
-template <int GS, int NT>
-__device__ __forceinline__ const double *lat_val_of(const Tabs &tb, Lds<GS, NT> &sm) {
-  return tb.lat_lds ? sm.lat_val : tb.lat_val;
-}
-template <int GS, int NT>
-__device__ __forceinline__ const int *lat_col_of(const Tabs &tb, Lds<GS, NT> &sm) {
-  return tb.lat_lds ? sm.lat_col : tb.lat_col;
+// f(values, columns) of the lattice operator's ELL layout: the LDS copy
+// when it is resident, else the tables in global memory. The two calls keep
+// each access in its own address space (a pointer that may be either would
+// make every access a flat one, which the LDS wait counter also waits for).
+template <int GS, int NT, typename F>
+__device__ __forceinline__ void with_lattice(const Tabs &tb, Lds<GS, NT> &sm, F &&f) {
+  if (tb.lat_lds)
+    f(sm.lat_val, sm.lat_col);
+  else
+    f(glb(tb.lat_val), glb(tb.lat_col));
 }
 
 struct ProposeOut {
@@ -269,14 +281,14 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
     }
   };
   auto load = [&](int pt, const double *src, double lv[NJ]) __attribute__((always_inline)) {
-    if (pt < 2) {  // the lattice vector H, in LDS
+    if (pt < 2) {  // the lattice vector H, in LDS (read from sm.H itself: no flat access)
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         int s = lane + j * GS;
         if constexpr (overlap)
-          lv[j] = src[min(s, Cs - 1)];
+          lv[j] = sm.H[min(s, Cs - 1)];
         else
-          lv[j] = s < C ? src[s] : 0.0;
+          lv[j] = s < C ? sm.H[s] : 0.0;
       }
     } else {
       const auto gsrc = glb(src);
@@ -332,9 +344,11 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
     for (int s = t; s < C; s += NT) sm.dk[s] = q * sm.sgnc[s] * (sm.latN[s] - sm.latO[s]);
     __syncthreads();
     double v = 0.0;
-    lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk, [&](int s, double y) {
-      v += sm.wdot[s] * sm.dk[s] * y;
-      sm.latO[s] = y;
+    with_lattice(tb, sm, [&](auto val, auto col) {
+      lattice_rows<NT>(tb, val, col, sm.dk, [&](int s, double y) {
+        v += sm.wdot[s] * sm.dk[s] * y;
+        sm.latO[s] = y;
+      });
     });
     return v;
   };
@@ -442,6 +456,273 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
   // needs no barrier of its own
   if (t == 0) ints[I_MASK] = 0;
   return out;
+}
+
+// One group of GS lanes: the table of T_n^m(x) (KIND 0) into the real-layout
+// buffer, through harmonics_core: each lane requests all the recurrence
+// constants of its column before the arithmetic starts and runs its rows to
+// the uniform bound, so the evaluation waits once for LDS instead of once
+// per row. The values are those of group_harmonics<GS, PM, 0, false>.
+template <int GS, int PM, typename R>
+__device__ __forceinline__ void group_harmonics_store(int lane, const Tabs &tb, const R *__restrict__ rec, R x, R y,
+                                                      R z, double *buf) {
+  const int m = lane;
+  harmonics_core<GS, PM, 0, R>(lane, tb, rec, x, y, z, R(1), [&](int, int n, double re, double im) {
+    buf[n * n + n + m] = re;
+    if (m > 0) buf[n * n + n - m] = im;
+  });
+}
+
+// The proposal of the whole-GPU chain's proposing workgroup (256 threads,
+// groups of 16 lanes, 2d + 2 <= 16 points): the terms of propose_wg with
+// the same arithmetic and the same order of every sum, in fewer phases.
+// Level point pt (2..2d+1) is held by group pt - 2; the two lattice points
+// by the two groups after them when those lie in the first three
+// wavefronts (d <= 5), else by groups 14 and 15. The last wavefront also
+// runs early() and forms the self-image terms.
+//   1. the coefficient rows of the level points and the first near-field
+//      records are requested;
+//   2. the harmonics of every point at once, the lattice points with their
+//      values from H; early(); the self-image terms, whose images are known
+//      from the cells alone: image nu of the old position is in the new near
+//      region exactly when the old leaf cell shifted by nu cells lies within
+//      one cell of the new leaf cell (the near field skips the same images);
+//   3. (barrier) dk is formed;
+//   4. (barrier) the rows of R dk (unrolled to the ELL width) with the
+//      quadratic lattice term, the near field, the level values from the
+//      requested rows, and spare() in the last wavefront;
+//   5. (barrier) after an accepted move the level rows are read only after
+//      gate() and their values formed then (one more barrier);
+//   6. lane 0 of the last wavefront adds the wavefront sums in order,
+//      assembles dE and calls decide(dE, singular); a last barrier makes
+//      the decision visible.
+// The sums are those of propose_wg: shuffle trees inside each wavefront,
+// then the wavefront totals in order, so dE is the same bit for bit.
+template <int GS, int PM, typename R, int NT, typename Early, typename Spare, typename Gate, typename Decide>
+__device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm,
+                                             Early &&early, Spare &&spare, Gate &&gate, Decide &&decide) {
+  constexpr int NG = NT / GS;
+  constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
+  static_assert(NT == WG_SINGLE && GS == 16, "the whole-GPU proposal shape");
+  const int Cs = tb.Cs, C = tb.C;
+  const int t = threadIdx.x, g = t / GS, lane = t % GS, wv = t >> 6, wl = t & 63;
+  int *ints = sm.ints;
+  const double a = ch.a, q = mv.q;
+  const int L = ch.L, d = ch.d, B = ch.B;
+  const int npts = 2 * d + 2;
+  const int nL = 1 << (L - 1);
+  const bool gated = gate.active();
+  const int lat0 = npts <= 12 ? npts - 2 : NG - 2;  // group of lattice point 0
+  // the point of this group: level points first, then the lattice points
+  const int pt = g < npts - 2 ? g + 2 : (g == lat0 ? 0 : (g == lat0 + 1 ? 1 : -1));
+  const bool last_free = npts <= 12;  // the last wavefront holds no point
+
+  // ---- 1. requests
+  double lv0[NJ];
+  if (!gated && pt >= 2) {
+    const int l = 2 + (pt - 2) / 2, sd = (pt - 2) % 2, n = 1 << (l - 1);
+    const int *c = sd ? mv.c1[l] : mv.c0[l];
+    const auto src = glb(ch.Ld) + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) lv0[j] = src[min(lane + j * GS, Cs - 1)];  // slots >= C are not used
+  }
+  double dold = 0.0, dnew = 0.0;
+  const int e = t >> 2, j0 = t & 3;
+  const int side = e / 27, ee = e % 27;
+  int w = 13, cnt = 0, id = -1, id1 = -1;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  size_t base = 0;
+  double4 pj = make_double4(0.0, 0.0, 0.0, 0.0), pj1 = pj;
+  if (t < 216) {
+    const int *c = side ? mv.c1[L] : mv.c0[L];
+    int b[3] = {c[0] + ee % 3 - 1, c[1] + (ee / 3) % 3 - 1, c[2] + ee / 9 - 1};
+    const int cell = lin3(nL, pmod(b[0], nL), pmod(b[1], nL), pmod(b[2], nL));
+    const int fx = pfloordiv(b[0], nL), fy = pfloordiv(b[1], nL), fz = pfloordiv(b[2], nL);
+    w = (fx + 1) + 3 * (fy + 1) + 9 * (fz + 1);
+    sx = fx * a;
+    sy = fy * a;
+    sz = fz * a;
+    base = (size_t)cell * B;
+    cnt = glb(ch.bin_cnt)[cell];
+    id = glb(ch.bin_id)[base + j0];
+    pj = ld_rec(ch.bin_p, base + j0);
+    id1 = glb(ch.bin_id)[base + j0 + 4];
+    pj1 = ld_rec(ch.bin_p, base + j0 + 4);
+  }
+
+  // ---- 2. the harmonics of every point; early(); the self-image terms
+  double hh = 1.0, *buf = nullptr;
+  const double *src = nullptr;
+  if (pt >= 0) {
+    double x[3];
+    if (pt < 2) {
+      buf = pt ? sm.latN : sm.latO;
+      const double *r = pt ? mv.rn : mv.r;
+      hh = a;
+      for (int k = 0; k < 3; ++k) x[k] = (r[k] - 0.5 * a) / a;
+    } else {
+      const int l = 2 + (pt - 2) / 2, sd = (pt - 2) % 2, n = 1 << (l - 1);
+      buf = sm.gbuf + (size_t)g * Cs;
+      hh = a / n;
+      const int *c = sd ? mv.c1[l] : mv.c0[l];
+      const double *r = sd ? mv.rn : mv.r;
+      for (int k = 0; k < 3; ++k) x[k] = (r[k] - (c[k] + 0.5) * hh) / hh;
+      src = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
+    }
+    if (pt < 2 || sizeof(R) == 8)  // the lattice term is FP64 in every mode
+      group_harmonics_store<GS, PM, double>(lane, tb, sm.rec, x[0], x[1], x[2], buf);
+    else
+      group_harmonics_store<GS, PM, R>(lane, tb, sm.template rec_of<R>(), (R)x[0], (R)x[1], (R)x[2], buf);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+  auto dot = [&](const double lv[NJ]) __attribute__((always_inline)) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      int s2 = lane + j * GS;
+      if (s2 < C) acc += lv[j] * sm.wl2p[s2] * buf[s2];
+    }
+    acc = group_sum<GS>(acc);
+    if (lane == 0) sm.vals[pt] = acc / hh;
+  };
+  if (pt >= 0 && pt < 2) {
+    double lv[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) lv[j] = sm.H[min(lane + j * GS, Cs - 1)];
+    dot(lv);
+  }
+  double self = 0.0;  // the last wavefront: sum of the self-image terms
+  if (wv == NT / 64 - 1) {
+    early(wl);
+    const int k = wl - 32;  // image k of the old position, lanes 32..58
+    if (k >= 0 && k < 27 && (!ch.free_space || k == 13)) {
+      const int f[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+      bool near = true;
+      for (int c = 0; c < 3; ++c) {
+        const int b = mv.c0[L][c] + f[c] * nL;
+        near = near && b >= mv.c1[L][c] - 1 && b <= mv.c1[L][c] + 1;
+      }
+      if (!near) {
+        const double dx = mv.rn[0] - (mv.r[0] + f[0] * a), dy = mv.rn[1] - (mv.r[1] + f[1] * a),
+                     dz = mv.rn[2] - (mv.r[2] + f[2] * a);
+        self = q * q / sqrt(dx * dx + dy * dy + dz * dz);
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) self += __shfl_xor(self, o, 64);
+  }
+  __syncthreads();
+
+  // ---- 3. dk = q (conj T(r') - conj T(r))
+  for (int s2 = t; s2 < C; s2 += NT) sm.dk[s2] = q * sm.sgnc[s2] * (sm.latN[s2] - sm.latO[s2]);
+  __syncthreads();
+
+  // ---- 4. R dk, near field, level values, spare
+  double latq = 0.0;
+  with_lattice(tb, sm, [&](auto val, auto col) {
+    lattice_rows_w<NT, ell_width(PM)>(tb, val, col, sm.dk, [&](int s2, double y) {
+      latq += sm.wdot[s2] * sm.dk[s2] * y;
+      sm.latO[s2] = y;  // R(dk), for the bookkeeping of an accept of this move
+    });
+  });
+  int singular = 0;
+  if (t < 216) {
+    if (ch.free_space && w != 13) cnt = 0;  // free space: no images
+    if (ee == 13 && j0 == 0) ints[side ? I_CNTNEW : I_CNTOLD] = cnt;
+    const double *xp = side ? mv.rn : mv.r;
+    for (int j = j0; j < cnt; j += 4) {
+      if (j == j0 + 4) {
+        id = id1;
+        pj = pj1;
+      } else if (j != j0) {
+        id = glb(ch.bin_id)[base + j];
+        pj = ld_rec(ch.bin_p, base + j);
+      }
+      if (side == 0 && ee == 13) {  // the moving charge's own leaf bin
+        if (id == mv.idx) ints[I_SLOTK] = j;
+        if (j == cnt - 1) {
+          ints[I_IDLAST] = id;
+          sm.stash[0] = pj;
+        }
+      }
+      // the moving charge itself: on the new side each of its images here
+      // goes with its self-image term (both left out), on the old side the
+      // charge without shift is not its own partner
+      if (id == mv.idx && (side || w == 13)) continue;
+      double dx = xp[0] - (pj.x + sx), dy = xp[1] - (pj.y + sy), dz = xp[2] - (pj.z + sz);
+      double r2 = dx * dx + dy * dy + dz * dz;
+      if (side && r2 == 0.0) singular = 1;
+      double v;
+      if constexpr (sizeof(R) == 4)
+        v = pj.w * (double)rsqrtf((float)r2);  // FP32 inverse distance of an FP64 difference
+      else
+        v = pj.w / sqrt(r2);
+      if (side) dnew += v; else dold += v;
+    }
+  }
+  if (singular) ints[I_SING] = 1;
+  if (!gated && pt >= 2) dot(lv0);
+  if (last_free && wv == NT / 64 - 1) spare(wl);
+  // wavefront partial sums (the shuffle trees of wg_sum4)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    dold += __shfl_xor(dold, o, 64);
+    dnew += __shfl_xor(dnew, o, 64);
+    latq += __shfl_xor(latq, o, 64);
+  }
+  if (wl == 0) {
+    sm.red[4 * wv + 0] = dold;
+    sm.red[4 * wv + 1] = dnew;
+    sm.red[4 * wv + 3] = latq;
+  }
+  __syncthreads();
+  if (!last_free && wv == NT / 64 - 1) spare(wl);
+
+  // ---- 5. after an accepted move: the level values once its rows are in place
+  if (gated) {
+    gate();
+    if (pt >= 2) {
+      double lv[NJ];
+      const auto gsrc = glb(src);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) lv[j] = gsrc[min(lane + j * GS, Cs - 1)];
+      dot(lv);
+    }
+    __syncthreads();
+  }
+
+  // ---- 6. assembly and decision (lane 0 of the last wavefront)
+  if (t == NT - 64) {
+    double part[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double sum = 0.0;
+      for (int w2 = 0; w2 < NT / 64; ++w2) sum += k == 2 ? (w2 == NT / 64 - 1 ? self : 0.0) : sm.red[4 * w2 + k];
+      part[k] = sum;
+    }
+    double dE = 0.0;
+    for (int l = 2; l <= L; ++l) {
+      const int po = 2 + 2 * (l - 2);
+      dE += q * (sm.vals[po + 1] - sm.vals[po]);
+    }
+    dE += q * (part[1] - part[0]);
+    dE += -part[2];
+    if (!ch.free_space) {
+      dE += q * q / a * tb.self_const;
+      dE += q * (sm.vals[1] - sm.vals[0]) + 0.5 * part[3] / a;
+      const double dr[3] = {mv.rn[0] - mv.r[0], mv.rn[1] - mv.r[1], mv.rn[2] - mv.r[2]};
+      const double Ddot = sm.st[0] * dr[0] + sm.st[1] * dr[1] + sm.st[2] * dr[2];
+      const double dd = dr[0] * dr[0] + dr[1] * dr[1] + dr[2] * dr[2];
+      dE += -2.0 * M_PI / (3.0 * a * a * a) * (2.0 * q * Ddot + q * q * dd);
+    } else if (!(mv.rn[0] >= 0.0 && mv.rn[0] < a && mv.rn[1] >= 0.0 && mv.rn[1] < a && mv.rn[2] >= 0.0 &&
+                 mv.rn[2] < a)) {
+      dE = INFINITY;  // free space: a move out of the box is never taken
+    }
+    decide(dE, ints[I_SING]);
+    ints[I_SING] = 0;
+  }
+  __syncthreads();
 }
 
 // An accepted move of a charge into another leaf cell whose bin is full
@@ -928,7 +1209,9 @@ __device__ __forceinline__ int accept_bookkeeping(const Chain &ch, const Tabs &t
       sm.K[s] += sm.dk[s];
     }
     __syncthreads();
-    lattice_rows<NT>(tb, lat_val_of(tb, sm), lat_col_of(tb, sm), sm.dk, [&](int s, double v) { sm.H[s] += v; });
+    with_lattice(tb, sm, [&](auto val, auto col) {
+      lattice_rows<NT>(tb, val, col, sm.dk, [&](int s, double v) { sm.H[s] += v; });
+    });
   }
   __syncthreads();
   return 0;

@@ -117,7 +117,7 @@ __device__ void accept_mp_wg(const Chain &ch, const Tabs &tb, const Move &mv, co
     if (same)
       group_harmonics_sum<GS, PM, 1>(lane, tb, rec, (mv.rn[0] - (c[0] + 0.5) * h) / h,
                                      (mv.rn[1] - (c[1] + 0.5) * h) / h, (mv.rn[2] - (c[2] + 0.5) * h) / h, q, cs);
-    double *row = ch.Mp + ch.mp_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * tb.Cs;
+    const auto row = glb(ch.Mp) + ch.mp_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * tb.Cs;
     flush_cols<PM, true>(lane, tb, cs, row);
   }
 }

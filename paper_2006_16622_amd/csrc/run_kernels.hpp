@@ -86,6 +86,45 @@ __device__ __forceinline__ void draw_into(const RunParams &rp, int c, int64_t t,
   nd.q = glb(ch.pq)[nd.idx];
 }
 
+// The random part of a draw (no memory of the chain's state): lane 0 forms
+// idx and the displacement (Philox counter (t, 0)), lane 1 the uniform
+// (counter (t, 1)), side by side; in list mode lane 0 reads the lists.
+struct RngDraw {
+  int64_t idx;
+  double d[3];
+  double u;
+};
+
+__device__ __forceinline__ void rng_into(const RunParams &rp, int c, int64_t t, int64_t N, double D, int lane,
+                                         RngDraw &out) {
+#pragma clang fp contract(off)
+  if (rp.list_idx) {
+    if (lane == 0) {
+      out.idx = rp.list_idx[t];
+      for (int k = 0; k < 3; ++k) out.d[k] = rp.list_pos[3 * t + k];
+      out.u = rp.list_u[t];
+    }
+    return;
+  }
+  if (lane >= 2) return;
+  // both counters in one instruction stream (lane 0: (t, 0), lane 1: (t, 1))
+  uint64_t w[4] = {(uint64_t)(rp.t0 + t), (uint64_t)lane, 0, 0};
+  philox4x64_10(w, rp.seed, (uint64_t)c);
+  const double two53 = 1.0 / 9007199254740992.0;
+  if (lane == 0) {
+    out.idx = (int64_t)__umul64hi(w[0], (uint64_t)N);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double f = (double)(w[k + 1] >> 11) * two53;
+      double two_f = 2.0 * f;
+      double centred = two_f - 1.0;
+      out.d[k] = D * centred;
+    }
+  } else {
+    out.u = (double)(w[0] >> 11) * two53;
+  }
+}
+
 // Build the move of a step from its draw (thread 0). If the previous step
 // accepted a move of the same particle after the draw was fetched, its new
 // position replaces the fetched one.
@@ -306,10 +345,25 @@ __host__ __device__ inline size_t spec_extra_bytes(int k, int NG, int Cs) {
 // fence would add a write-back of the whole L2 for plain stores, which the
 // helpers do not read.
 __device__ __forceinline__ void post_move(double *mb, unsigned *mvseq, unsigned num, const Move &mv) {
-  const auto slot = glb(mb) + 8 * (num & 1);
+  const auto slot = glb(mb) + 8 * (num & 3);
   const double v[8] = {(double)mv.idx, mv.q, mv.r[0], mv.r[1], mv.r[2], mv.rn[0], mv.rn[1], mv.rn[2]};
 #pragma unroll
   for (int k = 0; k < 8; ++k) __hip_atomic_store(slot + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  st_relaxed(mvseq, num);
+}
+
+// the same in two halves, so that the wavefront does not wait for its
+// stores where it would hold up the workgroup: post_issue writes the slot,
+// post_publish (later) waits for those stores and stores the number
+__device__ __forceinline__ void post_issue(double *mb, unsigned num, const Move &mv) {
+  const auto slot = glb(mb) + 8 * (num & 3);
+  const double v[8] = {(double)mv.idx, mv.q, mv.r[0], mv.r[1], mv.r[2], mv.rn[0], mv.rn[1], mv.rn[2]};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) __hip_atomic_store(slot + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void post_publish(unsigned *mvseq, unsigned num) {
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   st_relaxed(mvseq, num);
@@ -376,12 +430,17 @@ template <int GS, int PM, typename R>
 __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb, RunParams rp) {
   constexpr int NT = WG_SINGLE;
   constexpr int NG = NT / GS;
+  // groups of 16 lanes: the proposal of propose_fast, with the next move
+  // formed one step ahead (two move buffers); otherwise propose_wg
+  constexpr bool FAST = GS == 16;
   extern __shared__ double lds[];
-  __shared__ Move mv;
+  __shared__ Move mvs[2];  // workgroup 0: this step's move and the next; helpers use mvs[0]
+  Move &mv = mvs[0];
   __shared__ NextDraw nd;
-  __shared__ int s_flag, s_acc, s_ovf;
+  __shared__ RngDraw s_rng[2];  // workgroup 0: random part of the draws of the next steps, by step parity
+  __shared__ int s_flag, s_acc, s_ovf, s_sing;
   __shared__ unsigned s_seq;
-  __shared__ double s_u;
+  __shared__ double s_u, s_dE;
   __shared__ uint64_t s_ticks;
   __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
   const int t = threadIdx.x, w = blockIdx.x, G = gridDim.x;
@@ -410,32 +469,120 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     // the rows of the last accepted move may still be in flight (helpers
     // finish them while the next proposal forms its other terms)
     bool pending = false;
-    if (t == 0 && s0 < rp.steps) draw_into(rp, c, s0, ch, D, nd);
-    __syncthreads();
+    if constexpr (FAST) {
+      // the move of the first step, posted at once, and the random part of
+      // the next draw
+      if (s0 < rp.steps) {
+        if (t == 0) {
+          draw_into(rp, c, s0, ch, D, nd);
+          move_from_draw(rp, ch, nd, false, -1, prev_rn, mvs[0]);
+          mvs[0].u = nd.u;
+        }
+        if (t < 64 && s0 + 1 < rp.steps) rng_into(rp, c, s0 + 1, ch.N, D, t, s_rng[(s0 + 1) & 1]);
+        __syncthreads();
+        locate_move_par(ch, mvs[0]);
+        __syncthreads();
+        if (t == 0 && G > 1) post_move(mb, mvseq, 1u, mvs[0]);
+      }
+    } else {
+      if (t == 0 && s0 < rp.steps) draw_into(rp, c, s0, ch, D, nd);
+      __syncthreads();
+    }
+    int cur = 0;
+    double nxr[3] = {0, 0, 0}, nxq = 0;  // the last wavefront's lane 0: position and charge of the next draw
     for (int64_t step = s0; step < rp.steps; ++step) {
       uint64_t t_0 = __builtin_amdgcn_s_memrealtime();
       ++num;  // every thread keeps the move number
-      if (t == 0) {
-        move_from_draw(rp, ch, nd, prev_acc, prev_idx, prev_rn, mv);
-        s_u = nd.u;
-      }
-      __syncthreads();
-      locate_move_par(ch, mv);
-      __syncthreads();
-      const double u = s_u;
-      // the last wavefront of the proposal posts the move to the helpers
-      // first (its release fence is hidden behind the near field and the
-      // expansion evaluations) and later fetches the next draw
+      const bool more = step + 1 < rp.steps;
       HelperGate gate{pending, G, num, doneflag, &s_flag, &s_ticks};
-      ProposeOut po = propose_wg<GS, PM, R>(
-          ch, tb, mv, sm,
-          [&](int lane) {
-            if (lane == 0 && step + 1 < rp.steps) draw_into(rp, c, step + 1, ch, D, nd);
-          },
-          [&](int lane) {
-            if (lane == 0 && G > 1) post_move(mb, mvseq, num, mv);
-          },
-          gate);
+      double dE_step;
+      if constexpr (FAST) {
+        const Move &mc = mvs[cur];
+        Move &mn = mvs[cur ^ 1];
+        // The next move is formed during this proposal from the position
+        // its draw reads now (a later fix-up covers an accept of the same
+        // charge), posted (stores only) and published with this move's
+        // decision, so the helpers find it waiting when they finish this
+        // one. The random part of the draw after it is formed meanwhile.
+        RngDraw &rn1 = s_rng[(step + 1) & 1];
+        propose_fast<GS, PM, R, NT>(
+            ch, tb, mc, sm,
+            [&](int lane) {  // the position of the next draw; the draw after it
+              if (lane == 0 && more) {
+                const int64_t i = rn1.idx;
+                nxr[0] = glb(ch.px)[i];
+                nxr[1] = glb(ch.py)[i];
+                nxr[2] = glb(ch.pz)[i];
+                nxq = glb(ch.pq)[i];
+              }
+              if (step + 2 < rp.steps) rng_into(rp, c, step + 2, ch.N, D, lane, s_rng[step & 1]);
+            },
+            [&](int lane) {  // the next move, located and posted
+              if (!more) return;
+              if (lane == 0) {
+                nd.idx = rn1.idx;
+                for (int k = 0; k < 3; ++k) {
+                  nd.d[k] = rn1.d[k];
+                  nd.r[k] = nxr[k];
+                }
+                nd.u = rn1.u;
+                nd.q = nxq;
+                move_from_draw(rp, ch, nd, false, -1, prev_rn, mn);
+                mn.u = nd.u;
+              }
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+              locate_move_level(ch, mn, lane + 1);
+              if (lane == 0 && G > 1) post_issue(mb, num + 1, mn);
+            },
+            gate,
+            [&](double dE, int sing) {  // one thread (lane 0 of the last wavefront)
+              int acc = !sing && (mc.u < exp(-rp.beta * dE));
+              // a move that would overflow its new leaf bin is published as
+              // rejected (the helpers drop its rows) and the chain stops
+              s_ovf = acc && move_overflows(ch, mc, sm.ints);
+              if (s_ovf) acc = 0;
+              s_acc = acc;
+              s_dE = dE;
+              s_sing = sing;
+            });
+        dE_step = s_dE;
+        if (t == 0) {  // the counters live in thread 0, which writes the results
+          nprop += 1;
+          nsing += s_sing;
+        }
+      } else {
+        if (t == 0) {
+          move_from_draw(rp, ch, nd, prev_acc, prev_idx, prev_rn, mv);
+          s_u = nd.u;
+        }
+        __syncthreads();
+        locate_move_par(ch, mv);
+        __syncthreads();
+        const double u = s_u;
+        // the last wavefront of the proposal posts the move to the helpers
+        // first and later fetches the next draw
+        ProposeOut po = propose_wg<GS, PM, R>(
+            ch, tb, mv, sm,
+            [&](int lane) {
+              if (lane == 0 && more) draw_into(rp, c, step + 1, ch, D, nd);
+            },
+            [&](int lane) {
+              if (lane == 0 && G > 1) post_move(mb, mvseq, num, mv);
+            },
+            gate);
+        if (t == 0) {
+          int acc = !po.singular && (u < exp(-rp.beta * po.dE));
+          s_ovf = acc && move_overflows(ch, mv, sm.ints);
+          if (s_ovf) acc = 0;
+          s_acc = acc;
+          nprop += 1;
+          nsing += po.singular;
+        }
+        __syncthreads();
+        dE_step = po.dE;
+      }
+      const Move &m = mvs[FAST ? cur : 0];
       uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
       const uint64_t gate_ticks = pending ? s_ticks : 0;
       tick_prop += t_1 - t_0 - gate_ticks;
@@ -447,46 +594,39 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
           break;
         }
       }
-      if (t == 0) {
-        int acc = !po.singular && (u < exp(-rp.beta * po.dE));
-        // a move that would overflow its new leaf bin is published as
-        // rejected (the helpers drop its rows) and the chain stops
-        s_ovf = acc && move_overflows(ch, mv, sm.ints);
-        if (s_ovf) acc = 0;
-        s_acc = acc;
-        nprop += 1;
-        nsing += po.singular;
-      }
-      __syncthreads();
       prev_acc = s_acc;
       // the decision (a relaxed store: it publishes no data) and the traces
       // are stored by the last wavefront, so that the wavefront that starts
       // the next step has no store outstanding
       if (t == NT - 64) {
+        // the next move, posted during the proposal, is published first
+        // (its stores are long complete), unless this accepted move moved
+        // the same charge
+        if (FAST && G > 1 && more && !(prev_acc && (int)nd.idx == m.idx)) post_publish(mvseq, num + 1);
         if (G > 1) st_relaxed(dec, 2u * num + (unsigned)prev_acc);
         const int64_t o = (int64_t)c * rp.steps + step;
-        if (rp.tr_idx) glb(rp.tr_idx)[o] = mv.idx;
+        if (rp.tr_idx) glb(rp.tr_idx)[o] = m.idx;
         if (rp.tr_pos)
-          for (int k = 0; k < 3; ++k) glb(rp.tr_pos)[3 * o + k] = mv.rn[k];
-        if (rp.tr_dE) glb(rp.tr_dE)[o] = po.dE;
+          for (int k = 0; k < 3; ++k) glb(rp.tr_pos)[3 * o + k] = m.rn[k];
+        if (rp.tr_dE) glb(rp.tr_dE)[o] = dE_step;
         if (rp.tr_acc) glb(rp.tr_acc)[o] = (uint8_t)prev_acc;
         if (rp.tr_leaf) {
           int n = 1 << (ch.L - 1);
-          glb(rp.tr_leaf)[o] = lin3(n, mv.c1[ch.L][0], mv.c1[ch.L][1], mv.c1[ch.L][2]);
+          glb(rp.tr_leaf)[o] = lin3(n, m.c1[ch.L][0], m.c1[ch.L][1], m.c1[ch.L][2]);
         }
       }
       if (s_ovf) {
         status = -7;
         break;
       }
-      prev_idx = mv.idx;
-      for (int k = 0; k < 3; ++k) prev_rn[k] = mv.rn[k];
+      prev_idx = m.idx;
+      for (int k = 0; k < 3; ++k) prev_rn[k] = m.rn[k];
       if (prev_acc) {
-        if (G == 1) accept_all_wg<GS, PM, R>(ch, tb, mv, sm);
-        int ovf = accept_bookkeeping<GS, PM, true>(ch, tb, mv, po.dE, sm);
+        if (G == 1) accept_all_wg<GS, PM, R>(ch, tb, m, sm);
+        int ovf = accept_bookkeeping<GS, PM, true>(ch, tb, m, dE_step, sm);
         if (t == 0) {
           nacc += 1;
-          dEsum += po.dE;
+          dEsum += dE_step;
         }
         tick_acc += __builtin_amdgcn_s_memrealtime() - t_1;
         // the next proposal waits for the helpers (gate) only where it
@@ -497,6 +637,24 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
           break;
         }
         if (rp.acc_limit && ++acc_launch >= rp.acc_limit) break;
+      }
+      if constexpr (FAST) {
+        // the next move was formed from the position the draw read; if this
+        // accepted move moved the same charge, it is formed again from the
+        // new position (a uniform condition: LDS values)
+        if (more) {
+          if (prev_acc && (int)nd.idx == prev_idx) {
+            if (t == 0) {
+              move_from_draw(rp, ch, nd, true, prev_idx, prev_rn, mvs[cur ^ 1]);
+              mvs[cur ^ 1].u = nd.u;
+            }
+            __syncthreads();
+            locate_move_par(ch, mvs[cur ^ 1]);
+            __syncthreads();
+            if (t == 0 && G > 1) post_move(mb, mvseq, num + 1, mvs[cur ^ 1]);
+          }
+          cur ^= 1;
+        }
       }
     }
     // a helper must have stored the last accepted move before it is stopped
@@ -588,7 +746,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
       confirmed = last_acc;
     }
     if (t == 0) {
-      const auto slot = glb(mb) + 8 * (num & 1);
+      const auto slot = glb(mb) + 8 * (num & 3);
       double m[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) m[k] = slot[k];
