@@ -239,6 +239,29 @@ int fmm_mc_dump_multipoles(fmm_mc_t h, int level, double *out);
  * FMM_MC_EOVERFLOW. */
 int fmm_mc_resetup(fmm_mc_t h);
 
+/* Volume move, a move type beyond the single-charge displacement (the
+ * paper's outlook, Sec. 6): every position is scaled about the origin by
+ * s = new_box / box and the box side becomes new_box. The chain is first
+ * re-set up in FP64 from its current positions (as fmm_mc_resetup), then set
+ * up again from the same positions scaled by s in the new box; *dE (host)
+ * receives the difference of the two setup energies, U(scaled) - U(current).
+ * The scaled state becomes the chain's state (running and setup energy
+ * U(scaled)). The acceptance rule of the ensemble (for example
+ * exp(-beta (dE + P dV)) (V'/V)^N at constant pressure) belongs to the
+ * caller, as the Metropolis loop does (Sec. 4.1); to reject, call
+ * fmm_mc_rescale_undo. Free space: positions scale about the corner of the
+ * box at the origin, and stay inside it. Errors: FMM_MC_EINVAL for a box
+ * that is not finite and positive, FMM_MC_EOVERFLOW if a leaf bin overflows
+ * (the state is then the last one set up). */
+int fmm_mc_rescale(fmm_mc_t h, double new_box, double *dE);
+
+/* Undo the last fmm_mc_rescale of this chain: the box side and every
+ * position return to their values before it, bit for bit, and the
+ * expansions are set up afresh (FP64) from them. Valid only right after
+ * fmm_mc_rescale, before any other call that changes the chain (a run,
+ * an accept, a re-setup); FMM_MC_ESTATE otherwise. */
+int fmm_mc_rescale_undo(fmm_mc_t h);
+
 /* Result of fmm_mc_autotune. */
 typedef struct {
   int32_t m2l_rows;              /* chosen M2L output rows per workgroup: 96 or 192 */

@@ -82,6 +82,8 @@ SYMBOLS = {
     "fmm_mc_dump_locals": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "fmm_mc_dump_multipoles": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "fmm_mc_resetup": (ctypes.c_int, [_vp]),
+    "fmm_mc_rescale": (ctypes.c_int, [_vp, ctypes.c_double, _dp]),
+    "fmm_mc_rescale_undo": (ctypes.c_int, [_vp]),
     "fmm_mc_autotune": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                        ctypes.POINTER(Tuning)]),
     "fmm_mc_set_helpers": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -247,6 +249,18 @@ class Chain:
 
     def resetup(self):
         _check(load_library().fmm_mc_resetup(self._h), "fmm_mc_resetup")
+
+    def rescale(self, new_box: float) -> float:
+        """fmm_mc_rescale: volume move to box side new_box; returns dE"""
+        out = ctypes.c_double()
+        _check(load_library().fmm_mc_rescale(self._h, float(new_box), ctypes.byref(out)), "fmm_mc_rescale")
+        self._box_prev, self.box = self.box, float(new_box)
+        return out.value
+
+    def rescale_undo(self):
+        """fmm_mc_rescale_undo: back to the state before the last rescale"""
+        _check(load_library().fmm_mc_rescale_undo(self._h), "fmm_mc_rescale_undo")
+        self.box = self._box_prev
 
     def replay(self, idx, new_pos, u, beta: float):
         idx = np.ascontiguousarray(idx, dtype=np.int64)

@@ -42,6 +42,7 @@ struct Chain {
   int mixed;
   int free_space;               // free-space boundary conditions: no images, no lattice
   double a;                     // box side
+  double scale;                 // factor applied to the staged positions (1; a volume move's s)
   double inv_h[MAXL + 2];       // n_l / a on level l (cells per unit length), one IEEE division
   double *px, *py, *pz, *pq;    // particles by id (wrapped positions)
   int *leaf_of, *slot_of;

@@ -312,6 +312,10 @@ struct fmm_mc_ctx {
   int helpers = 0;                    // tuned helper workgroups of the whole-GPU run (0: all blocks)
   double last_ms[4] = {0, 0, 0, 0};
   bool ready = false;
+  // a volume move can be undone while the staging area still holds the
+  // positions before it (until any other call changes the state)
+  bool undo_ok = false;
+  double box_prev = 1.0;
   // buffers of the run entry points, allocated at setup (host_stats) or on
   // the first run of many chains led by this handle (grown when a run has
   // more chains than any before): launch arguments and per-chain results
@@ -624,6 +628,7 @@ static int create_chain(fmm_mc_t *out, void *dev_ws, size_t ws_bytes, void *hip_
   ch.mixed = (flags & FMM_MC_MIXED) ? 1 : 0;
   ch.free_space = (flags & FMM_MC_FREE_SPACE) ? 1 : 0;
   ch.a = box;
+  ch.scale = 1.0;
   for (int l = 0; l <= MAXL + 1; ++l) ch.inv_h[l] = double(1LL << (l > 0 ? l - 1 : 0)) / box;
   ch.px = (double *)(w + ly.off[O_PX]);
   ch.py = (double *)(w + ly.off[O_PY]);
@@ -782,6 +787,7 @@ int fmm_mc_setup_batch(fmm_mc_t *out, int n_chains, void *const *dev_ws, const s
 // The running energy becomes the fresh total energy; the setup energy stays.
 int fmm_mc_resetup(fmm_mc_t h) {
   if (!h || !h->ready) return FMM_MC_ESTATE;
+  h->undo_ok = false;
   if (!h->gexec) {
     if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     SetupLaunch S = single_launch(h);
@@ -805,6 +811,61 @@ int fmm_mc_resetup(fmm_mc_t h) {
   }
   HIPCHK(hipGraphLaunch(h->gexec, h->stream));
   return setup_status(h);
+}
+
+// the box side of a chain, in its host and device descriptors
+static int set_box(fmm_mc_t h, double box, double scale) {
+  h->box = box;
+  h->ch.a = box;
+  h->ch.scale = scale;
+  for (int l = 0; l <= MAXL + 1; ++l) h->ch.inv_h[l] = double(1LL << (l > 0 ? l - 1 : 0)) / box;
+  HIPCHK(hipMemcpyAsync(h->d_chain, &h->ch, sizeof(Chain), hipMemcpyHostToDevice, h->stream));
+  return 0;
+}
+
+// the setup pass from the staging area as it is (no restage): positions
+// times ch.scale, wrapped into the current box
+static int setup_from_stage(fmm_mc_t h) {
+  SetupLaunch S = single_launch(h);
+  S.restage = false;
+  S.energy_mode = 2;
+  S.fp32_m2l = false;  // FP64 in every mode, as every re-setup
+  int rc = enqueue_setup(S);
+  if (!rc) rc = setup_status(h);
+  return rc;
+}
+
+int fmm_mc_rescale(fmm_mc_t h, double new_box, double *dE) {
+  if (!h || !h->ready) return FMM_MC_ESTATE;
+  if (!dE || !(new_box > 0.0) || !std::isfinite(new_box)) return FMM_MC_EINVAL;
+  // a fresh setup of the current state (positions -> staging area ->
+  // expansions) and its energy
+  int rc = fmm_mc_resetup(h);
+  if (rc) return rc;
+  double U0 = 0.0, U1 = 0.0;
+  rc = fmm_mc_running_energy(h, &U0);
+  if (rc) return rc;
+  // the scaled state, set up from the same staging area
+  const double old_box = h->box;
+  rc = set_box(h, new_box, new_box / old_box);
+  if (!rc) rc = setup_from_stage(h);
+  // later re-setups stage the (scaled) positions as they are
+  if (!rc) rc = set_box(h, new_box, 1.0);
+  if (!rc) rc = fmm_mc_running_energy(h, &U1);
+  if (rc) return rc;
+  *dE = U1 - U0;
+  h->box_prev = old_box;
+  h->undo_ok = true;
+  return FMM_MC_OK;
+}
+
+int fmm_mc_rescale_undo(fmm_mc_t h) {
+  if (!h || !h->ready || !h->undo_ok) return FMM_MC_ESTATE;
+  h->undo_ok = false;
+  // the staging area still holds the positions before the volume move
+  int rc = set_box(h, h->box_prev, 1.0);
+  if (!rc) rc = setup_from_stage(h);
+  return rc;
 }
 
 int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
@@ -836,6 +897,7 @@ int fmm_mc_propose(fmm_mc_t h, int64_t idx, const double *new_pos, double *dE) {
 
 int fmm_mc_accept(fmm_mc_t h, int64_t idx, const double *new_pos, const double *dE_in, double *dE_out) {
   if (!h || !h->ready) return FMM_MC_ESTATE;
+  h->undo_ok = false;
   if (!new_pos || !finite3(new_pos)) return FMM_MC_EINVAL;
   if ((h->flags & FMM_MC_FREE_SPACE) && !in_box(new_pos, h->box)) return FMM_MC_EINVAL;
   if (idx < 0 || idx >= h->n) return FMM_MC_ERANGE;
@@ -924,6 +986,7 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
         chains[c]->flags != h0->flags)
       return FMM_MC_ESTATE;
   }
+  for (int c = 0; c < n_chains; ++c) chains[c]->undo_ok = false;
   const bool mixed = (h0->flags & FMM_MC_MIXED) != 0;
   const bool mp = (h0->flags & FMM_MC_MULTIPOLE) != 0;
   hipStream_t st = h0->stream;

@@ -47,14 +47,16 @@ __global__ void k_restage(const Chain *chains) {
   ch.stage[3 * ch.N + i] = ch.pq[i];
 }
 
-// wrap positions, locate leaf cells, count bin occupancy
+// scale (by ch.scale: 1, or the factor of a volume move; a product by 1 is
+// exact) and wrap the staged positions, locate leaf cells, count bin
+// occupancy
 __global__ void k_stage(const Chain *chains) {
   const Chain &ch = chains[blockIdx.y];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ch.N) return;
-  double x = wrap_coord(ch.stage[3 * i + 0], ch.a);
-  double y = wrap_coord(ch.stage[3 * i + 1], ch.a);
-  double z = wrap_coord(ch.stage[3 * i + 2], ch.a);
+  double x = wrap_coord(ch.stage[3 * i + 0] * ch.scale, ch.a);
+  double y = wrap_coord(ch.stage[3 * i + 1] * ch.scale, ch.a);
+  double z = wrap_coord(ch.stage[3 * i + 2] * ch.scale, ch.a);
   double q = ch.stage[3 * ch.N + i];
   ch.px[i] = x;
   ch.py[i] = y;
