@@ -19,14 +19,15 @@ Also measured in the same run and reported beside the headline value, each
 with its error against the Ewald oracle:
 * the rock-salt chain in mixed precision with an FP64 re-setup every 10^4
   accepts, and the drift each re-setup removes;
-* the rock-salt chain at p = 16, the degree at which its error against
-  Ewald falls below 1e-5 of RMS dE, in FP64 and in mixed precision;
+* the rock-salt chain at p = 19, the smallest degree at which its dE error
+  against Ewald falls below 1e-5 of RMS dE, in FP64 and in mixed precision;
 * the multipole-based variant (Alg. M.1-M.3) on the rock-salt chain, and
   the direct P2L setup (Alg. L.3);
 * the small (N = 10^3) and medium (N = 10^4, with setup time and a mixed
   rerun) single-chain workloads;
 * the batched form: 256 independent chains of uneven size and depth, set up
-  in one pass and run in one launch, in FP64 and in mixed precision, as
+  in one pass and run in one launch (one workgroup per chain), in FP64 and
+  in mixed precision, as
   aggregate steps/s, with the dE error of 8 sampled chains against Ewald
   and against the FP64 oracle;
 * the scaling sweep N = 10^3 .. 10^6 of the propose and accept times of the
@@ -54,6 +55,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1e-5 of RMS dE
 
 # HBM bytes per MH step of the timed single-chain launches of the default
 # command, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the counts of a
@@ -335,7 +337,8 @@ def c3_accuracy(wl, ew, count=200):
     ref = np.array([ew.propose(i, r) for i, r in moves])
     errs = {}
     for name, flags, p in (("f64", 0, 12), ("mixed", FMM_MC_MIXED, 12), ("direct_setup", FMM_MC_DIRECT_SETUP, 12),
-                           ("multipole", FMM_MC_MULTIPOLE, 12), ("f64_p16", 0, 16), ("mixed_p16", FMM_MC_MIXED, 16)):
+                           ("multipole", FMM_MC_MULTIPOLE, 12), (f"f64_p{P_GATE}", 0, P_GATE),
+                           (f"mixed_p{P_GATE}", FMM_MC_MIXED, P_GATE)):
         errs[name] = rel_rms(gpu_proposals(wl, moves, flags, p), ref)
     return errs, moves, ref
 
@@ -428,7 +431,7 @@ def run_batched(steps=10000, nchains=256, flags=0, resetup_every=0, seed=4):
             "setup_m2l_ms": m2l_ms,
             "nu_per_chain": [s["accepted"] / steps for s in st],
             "roofline": {"bound": "hbm", "achieved": abytes / kern / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": abytes / kern / 1e9 / HBM_PEAK_GBS, "kernel": "k_run_batched",
+                         "frac": abytes / kern / 1e9 / HBM_PEAK_GBS, "kernel": "k_run_chains",
                          "algorithmic_bytes": abytes},
             "n_range": [min(w.n for w in wls), max(w.n for w in wls)],
             "depths": {str(d): sum(1 for w in wls if w.depth == d) for d in sorted({w.depth for w in wls})},
@@ -707,11 +710,13 @@ def main():
         out["single_mixed"] = single_line(wl, args.steps, 1, mh, flags=FMM_MC_MIXED, resetup_every=10000)
         out["single_mixed"]["drift_removed_by_resetup"] = mixed_drift(wl)
         log(f"[bench] mixed {out['single_mixed']['value']:.0f} MH steps/s")
-        log("[bench] rock salt at p = 16 (meets the 1e-5 Ewald gate), FP64 and mixed")
-        out["single_p16"] = single_line(wl, max(1, args.steps // 4), 1, mh, p=16, tune=True)
-        out["single_p16_mixed"] = single_line(wl, max(1, args.steps // 4), 1, mh, flags=FMM_MC_MIXED, p=16,
-                                              resetup_every=10000)
-        log(f"[bench] p16 {out['single_p16']['value']:.0f} / mixed {out['single_p16_mixed']['value']:.0f}")
+        log(f"[bench] rock salt at p = {P_GATE} (the smallest degree whose dE meets the 1e-5 Ewald gate), "
+            "FP64 and mixed")
+        out[f"single_p{P_GATE}"] = single_line(wl, max(1, args.steps // 4), 1, mh, p=P_GATE, tune=True)
+        out[f"single_p{P_GATE}_mixed"] = single_line(wl, max(1, args.steps // 4), 1, mh, flags=FMM_MC_MIXED,
+                                                     p=P_GATE, resetup_every=10000)
+        log(f"[bench] p{P_GATE} {out[f'single_p{P_GATE}']['value']:.0f} / "
+            f"mixed {out[f'single_p{P_GATE}_mixed']['value']:.0f}")
         log("[bench] direct P2L setup (Alg. L.3)")
         from paper_2006_16622_amd import Chain
         torch.cuda.synchronize()
@@ -755,8 +760,10 @@ def main():
         out["dE_rel_rms_err_vs_ewald"] = errs
         out["dE_err_sample"] = ("200 proposals of the Philox stream from the initial rock-salt state; "
                                 "direct_setup: local expansions by Alg. L.3; multipole: Alg. M.1-M.3")
-        for key, line in (("f64", out), ("mixed", out.get("single_mixed")), ("f64_p16", out.get("single_p16")),
-                          ("mixed_p16", out.get("single_p16_mixed")), ("multipole", out.get("single_multipole"))):
+        for key, line in (("f64", out), ("mixed", out.get("single_mixed")),
+                          (f"f64_p{P_GATE}", out.get(f"single_p{P_GATE}")),
+                          (f"mixed_p{P_GATE}", out.get(f"single_p{P_GATE}_mixed")),
+                          ("multipole", out.get("single_multipole"))):
             if line is not None:
                 line["dE_rel_rms_err_vs_ewald"] = errs[key]
         log(f"[bench] errors vs Ewald: {errs}")

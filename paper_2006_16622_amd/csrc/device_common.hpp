@@ -436,6 +436,117 @@ __device__ __forceinline__ void flush_cols(int lane, const Tabs &tb, const ColSu
   }
 }
 
+// ------------------------------------------------------------------ P2L by columns
+// The P2L term (KIND 2 above) summed over many points into one target, in
+// a form with fewer operations per row, for the updates of an accepted move
+// (Alg. L.2). With T_n^m = (x + i y)^m P_n (P real, P_m = c_m,
+// P_n = A(n,m) z P_{n-1} - B(n,m) r^2 P_{n-2}), the term of row j (n = m + j)
+// of column m is
+//   c conj(T_n^m) / r^(2n+1) = alpha_j G S_j,  G = c conj(xi^m) / r,
+//   xi = (x + i y) / r^2,  S_0 = 1,  S_1 = z / r^2,
+//   S_j = (z / r^2) S_{j-1} + g_j S_{j-2} / r^2,
+//   g_j = -B(n,m) / (A(n,m) A(n-1,m)),  alpha_j = c_m A(m+1,m) ... A(n,m),
+// (S_j = P_n / (alpha_j r^(2j))). Lane m keeps g_j in registers for a run of
+// evaluations and sums G S_j over the points; alpha_j is applied once, when
+// the sums are written out. Rows beyond p have g_j = 0 and are never
+// written; neither are lanes beyond p.
+__device__ __forceinline__ double rsqrt_nr(double v) {
+  double y = __builtin_amdgcn_rsq(v);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {  // Newton steps for 1/sqrt(v)
+    const double e = fma(-v * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float v) {
+  float y = __builtin_amdgcn_rsqf(v);
+  const float e = fmaf(-v * y, y, 1.0f);
+  return fmaf(0.5f * y, e, y);
+}
+
+template <int PMAX, typename R>
+struct P2LCols {
+  R g[PMAX + 1];  // g[j], j >= 2
+};
+
+template <int PMAX, typename R>
+__device__ __forceinline__ void load_p2l_cols(int lane, const Tabs &tb, const double *rec, P2LCols<PMAX, R> &cols) {
+  const int p = tb.p, Cs = tb.Cs, m = lane;
+#pragma unroll
+  for (int j = 0; j <= PMAX; ++j) {
+    const int n = m + j;
+    cols.g[j] = R(0);
+    if (j >= 2 && n <= p) {
+      const int s = n * n + n + m, s1 = (n - 1) * (n - 1) + (n - 1) + m;
+      cols.g[j] = (R)(-rec[Cs + s] / (rec[s] * rec[s1]));
+    }
+  }
+}
+
+// add the terms of K points (v[k] in cell units from the target's centre,
+// charge c[k]) to the column sums; the K evaluations are interleaved row by
+// row, each row's sum taking them in the order k = 0 .. K-1
+template <int GS, int PMAX, typename R, int K>
+__device__ __forceinline__ void p2l_sum(int lane, const P2LCols<PMAX, R> &cols, const R (&v)[K][3], const R (&c)[K],
+                                        ColSum<PMAX> &acc) {
+  R zz[K], ir2[K], gr[K], gi[K], s1[K], s2[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const R x = v[k][0], y = v[k][1], z = v[k][2];
+    const R r2 = x * x + y * y + z * z;
+    const R ir = rsqrt_nr(r2);
+    ir2[k] = ir * ir;
+    zz[k] = z * ir2[k];
+    R wr = lane == 0 ? R(1) : x * ir2[k], wi = lane == 0 ? R(0) : y * ir2[k], unused = R(1);
+    scan_step<GS, 1, R>(lane, wr, wi, unused, false);  // xi^m
+    const R f = c[k] * ir;
+    gr[k] = f * wr;
+    gi[k] = -(f * wi);
+    s2[k] = R(1);
+    s1[k] = zz[k];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    acc.re[0] += (double)gr[k];
+    acc.im[0] += (double)gi[k];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    acc.re[1] += (double)(gr[k] * s1[k]);
+    acc.im[1] += (double)(gi[k] * s1[k]);
+  }
+#pragma unroll
+  for (int j = 2; j <= PMAX; ++j) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const R sj = fma(cols.g[j], ir2[k] * s2[k], zz[k] * s1[k]);
+      s2[k] = s1[k];
+      s1[k] = sj;
+      acc.re[j] += (double)(gr[k] * sj);
+      acc.im[j] += (double)(gi[k] * sj);
+    }
+  }
+}
+
+// write a group's P2L column sums, times alpha_j, into the real-layout buffer
+template <int PMAX, typename P>
+__device__ __forceinline__ void flush_p2l(int lane, const Tabs &tb, const double *rec, const ColSum<PMAX> &acc, P buf) {
+  const int p = tb.p, Cs = tb.Cs, m = lane;
+  if (m > p) return;
+  double alpha = rec[2 * Cs + m];
+#pragma unroll
+  for (int j = 0; j <= PMAX; ++j) {
+    const int n = m + j;
+    if (n <= p) {
+      const int sp = n * n + n + m;
+      if (j > 0) alpha *= rec[sp];
+      buf[sp] = alpha * acc.re[j];
+      if (m > 0) buf[n * n + n - m] = alpha * acc.im[j];
+    }
+  }
+}
+
 // sum over the GS lanes of a group (lanes of one wavefront)
 template <int GS>
 __device__ __forceinline__ double group_sum(double v) {

@@ -993,7 +993,10 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
   const Tabs &tb = h0->tables->tabs;
   const int GS = h0->GS;
   const bool single = (n_chains == 1 && mode != 1);
-  const int NT = single ? WG_SINGLE : WG_BATCH;
+  // many chains with 16-lane groups run the whole-GPU chain's workgroup-0
+  // loop, one workgroup per chain (k_run_chains); the others k_run_batched
+  const bool lead = !single && !mp && GS == 16;
+  const int NT = single || lead ? WG_SINGLE : WG_BATCH;
   size_t shm = smem_bytes(GS, tb, NT);
   const RunArea ra(n_chains);
   char *dev = nullptr, *host = nullptr;
@@ -1142,9 +1145,13 @@ static int run_chains(fmm_mc_t *chains, int n_chains, int64_t steps, uint64_t se
         });
       } else {
         with_run_variant(h0->p, mixed, [&](auto gs, auto pm, auto rt) {
-          hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<decltype(gs)::value, decltype(pm)::value,
-                                                           typename decltype(rt)::type>),
-                             dim3(na), dim3(NT), shm, st, d_chains, tb, rp);
+          constexpr int gsv = decltype(gs)::value;
+          if constexpr (gsv == 16)  // lead
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_chains<gsv, decltype(pm)::value, typename decltype(rt)::type>),
+                               dim3(na), dim3(NT), shm, st, d_chains, tb, rp);
+          else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_run_batched<gsv, decltype(pm)::value, typename decltype(rt)::type>),
+                               dim3(na), dim3(NT), shm, st, d_chains, tb, rp);
         });
       }
     }

@@ -792,7 +792,7 @@ __device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, c
   it.active = 0;
   it.two = 0;
   const int n = 1 << (l - 1);
-  const double h = ch.a / n;
+  const double inv_h = ch.inv_h[l];
   const int side = item / 189, k189 = item % 189;
   const int *c = side ? mv.c1[l] : mv.c0[l];
   const int *co = side ? mv.c0[l] : mv.c1[l];
@@ -807,11 +807,11 @@ __device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, c
   it.active = 1;
   it.dst = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * tb.Cs;
   const double *x = side ? mv.rn : mv.r;
-  for (int k = 0; k < 3; ++k) it.v0[k] = (x[k] - (b[k] + 0.5) * h) / h;
+  for (int k = 0; k < 3; ++k) it.v0[k] = fma(x[k], inv_h, -(b[k] + 0.5));
   it.q0 = side ? mv.q : -mv.q;
   if (side == 0 && other) {
     it.two = 1;
-    for (int k = 0; k < 3; ++k) it.v1[k] = (mv.rn[k] - (b_other[k] + 0.5) * h) / h;
+    for (int k = 0; k < 3; ++k) it.v1[k] = fma(mv.rn[k], inv_h, -(b_other[k] + 0.5));
     it.q1 = mv.q;
   }
   return it;
@@ -896,7 +896,6 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
   if (coarse_l) {
     // ---- one stored cell of level 2 or 3: all its images in both lists
     const int l = coarse_l, n = 1 << (l - 1);
-    const double h = a / n;
     int s[3] = {s_lin % n, (s_lin / n) % n, s_lin / (n * n)};
     double *row = ch.Ld + ch.ld_off[l] + (size_t)s_lin * Cs;
     double old = glb(row)[min(t, Cs - 1)];  // used for t < C (C <= NT for the 16-lane groups)
@@ -927,22 +926,33 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
       if (t == 0) lst[0] = __popcll(bal);
     }
     __syncthreads();
-    // each group sums its candidates in registers (in candidate order) and
-    // writes its column sums once
+    // each group sums its candidates in registers (P2L by columns, two at a
+    // time) and writes its column sums once
     const int nv = lst[0];
+    P2LCols<PM, R> cols;
+    load_p2l_cols<PM, R>(lane, tb, sm.rec, cols);
+    auto cand_pt = [&](int cand, R v[3], R &c) __attribute__((always_inline)) {
+      const int side = cand / 27, e = cand % 27;
+      const int w[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
+      const double *x = side ? mv.rn : mv.r;
+      for (int k = 0; k < 3; ++k) v[k] = (R)fma(x[k], ch.inv_h[l], -((s[k] + n * w[k]) + 0.5));
+      c = (R)(side ? q : -q);
+    };
     ColSum<PM> cs;
     cs.zero();
-    for (int i = g; i < nv; i += NG) {
-      int cand = lst[1 + i];
-      int side = cand / 27, e = cand % 27;
-      int w[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
-      const double *x = side ? mv.rn : mv.r;
-      double v[3];
-      for (int k = 0; k < 3; ++k) v[k] = (x[k] - ((s[k] + n * w[k]) + 0.5) * h) / h;
-      group_harmonics_sum<GS, PM, 2, R>(lane, tb, sm.template rec_of<R>(), (R)v[0], (R)v[1], (R)v[2],
-                                        (R)(side ? q : -q), cs);
+    int i = g;
+    for (; i + NG < nv; i += 2 * NG) {
+      R v[2][3], c[2];
+      cand_pt(lst[1 + i], v[0], c[0]);
+      cand_pt(lst[1 + i + NG], v[1], c[1]);
+      p2l_sum<GS, PM, R, 2>(lane, cols, v, c, cs);
     }
-    flush_cols<PM, false>(lane, tb, cs, acc + (size_t)g * Cs);
+    if (i < nv) {
+      R v[1][3], c[1];
+      cand_pt(lst[1 + i], v[0], c[0]);
+      p2l_sum<GS, PM, R, 1>(lane, cols, v, c, cs);
+    }
+    flush_p2l<PM>(lane, tb, sm.rec, cs, acc + (size_t)g * Cs);
     __syncthreads();
     for (int k = t; k < C; k += NT) {
       double sum = 0.0;
@@ -970,14 +980,20 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
     old[j] = glb(it.dst)[min(k, Cs - 1)];
   }
   // the one or two contributions are summed in registers, then written once
+  P2LCols<PM, R> cols;
+  load_p2l_cols<PM, R>(lane, tb, sm.rec, cols);
   ColSum<PM> cs;
   cs.zero();
-  group_harmonics_sum<GS, PM, 2, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
-                                    (R)it.q0, cs);
-  if (it.two)
-    group_harmonics_sum<GS, PM, 2, R>(lane, tb, sm.template rec_of<R>(), (R)it.v1[0], (R)it.v1[1], (R)it.v1[2],
-                                      (R)it.q1, cs);
-  flush_cols<PM, false>(lane, tb, cs, buf);
+  if (it.two) {
+    const R v[2][3] = {{(R)it.v0[0], (R)it.v0[1], (R)it.v0[2]}, {(R)it.v1[0], (R)it.v1[1], (R)it.v1[2]}};
+    const R c[2] = {(R)it.q0, (R)it.q1};
+    p2l_sum<GS, PM, R, 2>(lane, cols, v, c, cs);
+  } else {
+    const R v[1][3] = {{(R)it.v0[0], (R)it.v0[1], (R)it.v0[2]}};
+    const R c[1] = {(R)it.q0};
+    p2l_sum<GS, PM, R, 1>(lane, cols, v, c, cs);
+  }
+  flush_p2l<PM>(lane, tb, sm.rec, cs, buf);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
@@ -1023,38 +1039,76 @@ __device__ void accept_block(const Chain &ch, const Tabs &tb, const Move &mv, in
 // The whole update of an accepted move by one workgroup (one chain per
 // workgroup): every group works through its own share of targets without
 // workgroup barriers between them. Level 2: each of the 8 stored cells is
-// split over NG/8 groups (partial sums added in a fixed order); level 3: 64
-// stored cells over the groups; levels >= 4: the items of both interaction
-// lists over the groups.
-//
-// With PIPE (the batched kernel) each group requests the target of its next
-// fine item before it forms the current one (no two items share a target,
-// so the early read sees the value before this move); the results are the
-// same bit for bit.
-template <int GS, int PM, typename R, int NT, bool PIPE = false>
+// split over NG/8 groups (candidates taken round robin, partial sums added
+// in a fixed order); level 3: 64 stored cells over the groups; levels >= 4:
+// the items of both interaction lists over the groups. A group sums the
+// terms of a target in registers (P2L by columns, two points at a time),
+// writes the sums once to its LDS buffer and adds them to the target row,
+// whose loads are issued before the terms are formed.
+template <int GS, int PM, typename R, int NT>
 __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm) {
   constexpr int NG = NT / GS;
   constexpr int NJ = (PM + 1) * (PM + 1) / GS + 1;
-  constexpr int SPLIT2 = NG / 8;  // NG is 16 or 8
-  static_assert(NG % 8 == 0, "groups per workgroup");
+  constexpr int SPLIT2 = NG / 8;  // NG is 32, 16 or 8
+  static_assert(NG % 8 == 0 && SPLIT2 <= 4, "groups per workgroup");
   const int Cs = tb.Cs, C = tb.C;
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
   const int L = ch.L;
-  const double a = ch.a;
   double *buf = sm.gbuf + (size_t)g * Cs;
-  // ---- level 2: group g sums part g / 8 of the contributions to cell g % 8
+  P2LCols<PM, R> cols;
+  load_p2l_cols<PM, R>(lane, tb, sm.rec, cols);
+  // the point of candidate `cand` (side 27 side + image) of stored cell s3
+  // of coarse level l, in cell units from the image's centre
+  auto coarse_pt = [&](int l, const int s3[3], int cand, R v[3], R &c) __attribute__((always_inline)) {
+    const int n = 1 << (l - 1);
+    const int side = cand / 27, e = cand % 27;
+    const int w[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
+    const double *x = side ? mv.rn : mv.r;
+    for (int k = 0; k < 3; ++k) v[k] = (R)fma(x[k], ch.inv_h[l], -((s3[k] + n * w[k]) + 0.5));
+    c = (R)(side ? mv.q : -mv.q);
+  };
+  // the terms of every candidate in mask m, two at a time
+  auto coarse_sum = [&](int l, const int s3[3], uint64_t m, ColSum<PM> &cs) __attribute__((always_inline)) {
+    while (m) {
+      const int c0 = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      if (m) {
+        const int c1 = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        R v[2][3], q[2];
+        coarse_pt(l, s3, c0, v[0], q[0]);
+        coarse_pt(l, s3, c1, v[1], q[1]);
+        p2l_sum<GS, PM, R, 2>(lane, cols, v, q, cs);
+      } else {
+        R v[1][3], q[1];
+        coarse_pt(l, s3, c0, v[0], q[0]);
+        p2l_sum<GS, PM, R, 1>(lane, cols, v, q, cs);
+      }
+    }
+  };
+  // row := old + sums (old read slot by slot before the sums were formed)
+  auto finish_row = [&](gptr<double> dst, const double old[NJ], const ColSum<PM> &cs) __attribute__((always_inline)) {
+    flush_p2l<PM>(lane, tb, sm.rec, cs, buf);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      int k = lane + j * GS;
+      if (k < C) dst[k] = old[j] + buf[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  };
+  // ---- level 2: group g sums the candidates cand = part (mod SPLIT2) of cell g % 8
   {
     const int cell = g % 8, part = g / 8;
     const int s3[3] = {cell % 2, (cell / 2) % 2, cell / 4};
-    uint64_t m = coarse_mask<GS>(mv, 2, s3, lane, ch.free_space);
-    for (int k = lane; k < Cs; k += GS) buf[k] = 0.0;
-    __builtin_amdgcn_wave_barrier();
-    int idx = 0;
-    while (m) {
-      int cand = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1;
-      if (idx++ % SPLIT2 == part) coarse_contrib<GS, PM, R>(tb, sm.template rec_of<R>(), mv, 2, s3, cand, a, lane, buf);
-    }
+    const uint64_t every = SPLIT2 == 4 ? 0x1111111111111111ull : SPLIT2 == 2 ? 0x5555555555555555ull : ~0ull;
+    const uint64_t m = coarse_mask<GS>(mv, 2, s3, lane, ch.free_space) & (every << part);
+    ColSum<PM> cs;
+    cs.zero();
+    coarse_sum(2, s3, m, cs);
+    flush_p2l<PM>(lane, tb, sm.rec, cs, buf);
   }
   __syncthreads();
   for (int i = t; i < 8 * C; i += NT) {
@@ -1072,64 +1126,35 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
       const auto dst = glb(ch.Ld) + ch.ld_off[3] + (size_t)cell * Cs;
       double old[NJ];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        int k = lane + j * GS;
-        old[j] = k < C ? dst[k] : 0.0;
-      }
-      uint64_t m = coarse_mask<GS>(mv, 3, s3, lane, ch.free_space);
-      for (int k = lane; k < Cs; k += GS) buf[k] = 0.0;
-      __builtin_amdgcn_wave_barrier();
-      while (m) {
-        int cand = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        coarse_contrib<GS, PM, R>(tb, sm.template rec_of<R>(), mv, 3, s3, cand, a, lane, buf);
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        int k = lane + j * GS;
-        if (k < C) dst[k] = old[j] + buf[k];
-      }
-      __builtin_amdgcn_wave_barrier();
+      for (int j = 0; j < NJ; ++j) old[j] = dst[min(lane + j * GS, Cs - 1)];  // slots >= C are not used
+      const uint64_t m = coarse_mask<GS>(mv, 3, s3, lane, ch.free_space);
+      ColSum<PM> cs;
+      cs.zero();
+      coarse_sum(3, s3, m, cs);
+      finish_row(dst, old, cs);
     }
   }
-  // ---- levels >= 4: each item's target is loaded while its harmonics are formed
+  // ---- levels >= 4: one or two terms per item's own target
   const int nfine = L >= 4 ? (L - 3) * 378 : 0;
-  FineItem nx;
-  double nold[NJ];
-  auto fetch = [&](int ii) {
-    nx = fine_item(ch, tb, sm.il_off, mv, 4 + ii / 378, ii % 378);
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      int k = lane + j * GS;
-      nold[j] = nx.active && k < C ? glb(nx.dst)[k] : 0.0;
-    }
-  };
-  if (PIPE && g < nfine) fetch(g);
   for (int i = g; i < nfine; i += NG) {
-    if (!PIPE) fetch(i);
-    const FineItem it = nx;
+    const FineItem it = fine_item(ch, tb, sm.il_off, mv, 4 + i / 378, i % 378);
+    if (!it.active) continue;
+    const auto dst = glb(it.dst);
     double old[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) old[j] = nold[j];
-    if (PIPE && i + NG < nfine) fetch(i + NG);
-    if (!it.active) continue;
-    group_harmonics<GS, PM, 2, false, R>(lane, tb, sm.template rec_of<R>(), (R)it.v0[0], (R)it.v0[1], (R)it.v0[2],
-                                         (R)it.q0, buf);
+    for (int j = 0; j < NJ; ++j) old[j] = dst[min(lane + j * GS, Cs - 1)];
+    ColSum<PM> cs;
+    cs.zero();
     if (it.two) {
-      __builtin_amdgcn_wave_barrier();
-      group_harmonics<GS, PM, 2, true, R>(lane, tb, sm.template rec_of<R>(), (R)it.v1[0], (R)it.v1[1],
-                                          (R)it.v1[2], (R)it.q1, buf);
+      const R v[2][3] = {{(R)it.v0[0], (R)it.v0[1], (R)it.v0[2]}, {(R)it.v1[0], (R)it.v1[1], (R)it.v1[2]}};
+      const R q[2] = {(R)it.q0, (R)it.q1};
+      p2l_sum<GS, PM, R, 2>(lane, cols, v, q, cs);
+    } else {
+      const R v[1][3] = {{(R)it.v0[0], (R)it.v0[1], (R)it.v0[2]}};
+      const R q[1] = {(R)it.q0};
+      p2l_sum<GS, PM, R, 1>(lane, cols, v, q, cs);
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      int k = lane + j * GS;
-      if (k < C) glb(it.dst)[k] = old[j] + buf[k];
-    }
-    __builtin_amdgcn_wave_barrier();
+    finish_row(dst, old, cs);
   }
   __syncthreads();
 }

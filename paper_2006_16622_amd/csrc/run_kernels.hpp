@@ -227,7 +227,7 @@ k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
       if constexpr (MP)
         accept_mp_wg<GS, PM, NT>(ch, tb, mv, sm.rec);
       else
-        accept_all_wg<GS, PM, R, NT, true>(ch, tb, mv, sm);
+        accept_all_wg<GS, PM, R, NT>(ch, tb, mv, sm);
       int ovf = accept_bookkeeping<GS, PM, !MP>(ch, tb, mv, po.dE, sm);
       if (t == 0) {
         nacc += 1;
@@ -426,8 +426,8 @@ struct HelperGate {
 // rejected move (whose rows are dropped). A helper that finds a move
 // already decided rejected skips it. Every wait is bounded; on time-out the
 // chain stops with an error status.
-template <int GS, int PM, typename R>
-__global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb, RunParams rp) {
+template <int GS, int PM, typename R, bool BATCH>
+__device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb, const RunParams &rp) {
   constexpr int NT = WG_SINGLE;
   constexpr int NG = NT / GS;
   // groups of 16 lanes: the proposal of propose_fast, with the next move
@@ -443,7 +443,9 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   __shared__ double s_u, s_dE;
   __shared__ uint64_t s_ticks;
   __shared__ Chain chl;  // the chain's descriptor, indexed by level without scratch
-  const int t = threadIdx.x, w = blockIdx.x, G = gridDim.x;
+  // BATCH: every workgroup runs its own chain alone (slot blockIdx.x)
+  const int t = threadIdx.x, w = BATCH ? 0 : (int)blockIdx.x, G = BATCH ? 1 : (int)gridDim.x;
+  const int slot = BATCH ? (int)blockIdx.x : 0;
   if (t == 0) chl = ch_arg;
   __syncthreads();
   const Chain &ch = chl;
@@ -455,7 +457,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
   stage_lds(ch, tb, sm, w == 0);
   __syncthreads();
   if (w == 0) {
-    const int c = rp.chain_id ? rp.chain_id[0] : 0;
+    const int c = rp.chain_id ? rp.chain_id[slot] : slot;
     const double D = run_max_step(rp, c);
     double nprop = 0, nacc = 0, nsing = 0, dEsum = 0;
     int status = 0;
@@ -464,7 +466,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     bool prev_acc = false;
     int prev_idx = -1;
     double prev_rn[3] = {0, 0, 0};
-    const int64_t s0 = run_first(rp, 0);
+    const int64_t s0 = run_first(rp, slot);
     int64_t acc_launch = 0;
     // the rows of the last accepted move may still be in flight (helpers
     // finish them while the next proposal forms its other terms)
@@ -670,15 +672,16 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
     __syncthreads();
     writeback_lds(ch, tb, sm);
     if (t == 0) {
-      glb(rp.stats)[0] = nprop;
-      glb(rp.stats)[1] = nacc;
-      glb(rp.stats)[2] = nsing;
-      glb(rp.stats)[3] = dEsum;
-      glb(rp.stats)[4] = status;
-      glb(rp.stats)[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
-      glb(rp.stats)[6] = tick_acc * 0.01;
-      glb(rp.stats)[7] = tick_wait * 0.01;
-      glb(rp.stats)[8] = sm.st[3];
+      const auto st = glb(rp.stats) + RUN_NSTAT * slot;
+      st[0] = nprop;
+      st[1] = nacc;
+      st[2] = nsing;
+      st[3] = dEsum;
+      st[4] = status;
+      st[5] = tick_prop * 0.01;  // microseconds (100 MHz clock)
+      st[6] = tick_acc * 0.01;
+      st[7] = tick_wait * 0.01;
+      st[8] = sm.st[3];
     }
     return;
   }
@@ -832,6 +835,19 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb,
 // sync[2] stop, sync[3] error, sync[64 + w] done flag of helper w; the move
 // is in mailbox slot number & 1, which is rewritten only after every helper
 // has finished the move after it. Every wait is bounded.
+template <int GS, int PM, typename R>
+__global__ void __launch_bounds__(WG_SINGLE) k_run_single(Chain ch_arg, Tabs tb, RunParams rp) {
+  run_chain_wg<GS, PM, R, false>(ch_arg, tb, rp);
+}
+
+// Many independent chains, one workgroup each: the loop of the whole-GPU
+// chain's workgroup 0 without helpers (its proposal, then the whole update
+// of an accepted move by the workgroup itself).
+template <int GS, int PM, typename R>
+__global__ void __launch_bounds__(WG_SINGLE) k_run_chains(const Chain *chains, Tabs tb, RunParams rp) {
+  run_chain_wg<GS, PM, R, true>(chains[blockIdx.x], tb, rp);
+}
+
 template <int GS, int PM>
 __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs tb, RunParams rp) {
   constexpr int NT = WG_SINGLE;
