@@ -57,16 +57,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1e-5 of RMS dE
 
-# HBM bytes per MH step of the timed single-chain launches of the default
-# command, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the counts of a
-# plain 1 GiB device copy (FETCH_SIZE reads half the copied bytes,
-# WRITE_SIZE all of them); the per-step figure depends on the acceptance
-# rate of the run, which the fixed proposal stream fixes. Valid only for
-# the kernel sources they were taken on; otherwise the traffic is null.
+# HBM bytes per MH step of the timed launches of the default command, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the counts of a plain 1 GiB
+# device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of
+# them): the 20 single-chain launches (k_run_single) and the batched FP64
+# launch (k_run_chains, 256 chains x 10^4 steps). The per-step figures depend
+# on the acceptance rate, which the fixed proposal stream fixes. Valid only
+# for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": None,
-    "fetch_bytes_per_step": None,
-    "write_bytes_per_step": None,
+    "src_sha256": "81379cbd5c076f439ff784e4f1da5017f533236052aed9517d2462924333bde5",
+    "fetch_bytes_per_step": 760097.0,
+    "write_bytes_per_step": 438489.0,
+    "batched_fetch_bytes_per_step": 209421.0,
+    "batched_write_bytes_per_step": 188500.0,
 }
 
 
@@ -81,11 +84,14 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(mh_steps):
+def measured_traffic(mh_steps, batched=False):
+    """HBM bytes (FETCH + WRITE, scaled) of a launch of mh_steps MH steps,
+    or None when the kernel sources differ from those the counters came from"""
     m = MEASURED_TRAFFIC
     if m["src_sha256"] is None or kernel_sources_sha256() != m["src_sha256"]:
         return None
-    return mh_steps * (m["fetch_bytes_per_step"] + m["write_bytes_per_step"])
+    pre = "batched_" if batched else ""
+    return mh_steps * (m[pre + "fetch_bytes_per_step"] + m[pre + "write_bytes_per_step"])
 
 
 def log(*a):
@@ -267,7 +273,9 @@ def headline(wl, steps, warmup, mh):
         "t_acc_us": (s0["t_accept_us"] + s0["t_wait_us"]) / max(1, s0["accepted"]),
         "setup_ms": t_setup * 1e3, "setup_m2l_ms": m2l_ms, "autotune": tune,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(total),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(mh),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+                     "algorithmic_bytes_per_launch": total_bytes / steps,
                      "algorithmic_bytes": total_bytes, "kernel": "k_run_single", "kernel_s": kern,
                      "launches": steps, "mh_steps_per_launch": mh,
                      "bytes_per_proposal": prop_b, "bytes_per_accept": acc_b,
@@ -432,7 +440,9 @@ def run_batched(steps=10000, nchains=256, flags=0, resetup_every=0, seed=4):
             "nu_per_chain": [s["accepted"] / steps for s in st],
             "roofline": {"bound": "hbm", "achieved": abytes / kern / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": abytes / kern / 1e9 / HBM_PEAK_GBS, "kernel": "k_run_chains",
-                         "algorithmic_bytes": abytes},
+                         "algorithmic_bytes": abytes,
+                         "traffic": measured_traffic(nchains * steps, batched=True) if not flags else None,
+                         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"},
             "n_range": [min(w.n for w in wls), max(w.n for w in wls)],
             "depths": {str(d): sum(1 for w in wls if w.depth == d) for d in sorted({w.depth for w in wls})},
             "status": [s["status"] for s in st if s["status"] != 0][:4]}

@@ -586,12 +586,6 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
     acc = group_sum<GS>(acc);
     if (lane == 0) sm.vals[pt] = acc / hh;
   };
-  if (pt >= 0 && pt < 2) {
-    double lv[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) lv[j] = sm.H[min(lane + j * GS, Cs - 1)];
-    dot(lv);
-  }
   double self = 0.0;  // the last wavefront: sum of the self-image terms
   if (wv == NT / 64 - 1) {
     early(wl);
@@ -614,8 +608,14 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
   }
   __syncthreads();
 
-  // ---- 3. dk = q (conj T(r') - conj T(r))
-  for (int s2 = t; s2 < C; s2 += NT) sm.dk[s2] = q * sm.sgnc[s2] * (sm.latN[s2] - sm.latO[s2]);
+  // ---- 3. dk = q (conj T(r') - conj T(r)); the two lattice values H . T,
+  // one slot per thread, summed with the wavefront sums below
+  double lato = 0.0, latn = 0.0;
+  for (int s2 = t; s2 < C; s2 += NT) {
+    sm.dk[s2] = q * sm.sgnc[s2] * (sm.latN[s2] - sm.latO[s2]);
+    lato += sm.H[s2] * sm.wl2p[s2] * sm.latO[s2];
+    latn += sm.H[s2] * sm.wl2p[s2] * sm.latN[s2];
+  }
   __syncthreads();
 
   // ---- 4. R dk, near field, level values, spare
@@ -670,11 +670,15 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
     dold += __shfl_xor(dold, o, 64);
     dnew += __shfl_xor(dnew, o, 64);
     latq += __shfl_xor(latq, o, 64);
+    lato += __shfl_xor(lato, o, 64);
+    latn += __shfl_xor(latn, o, 64);
   }
   if (wl == 0) {
     sm.red[4 * wv + 0] = dold;
     sm.red[4 * wv + 1] = dnew;
     sm.red[4 * wv + 3] = latq;
+    sm.red[16 + 2 * wv] = lato;
+    sm.red[17 + 2 * wv] = latn;
   }
   __syncthreads();
   if (!last_free && wv == NT / 64 - 1) spare(wl);
@@ -710,7 +714,12 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
     dE += -part[2];
     if (!ch.free_space) {
       dE += q * q / a * tb.self_const;
-      dE += q * (sm.vals[1] - sm.vals[0]) + 0.5 * part[3] / a;
+      double vo = 0.0, vn = 0.0;
+      for (int w2 = 0; w2 < NT / 64; ++w2) {
+        vo += sm.red[16 + 2 * w2];
+        vn += sm.red[17 + 2 * w2];
+      }
+      dE += q * (vn / a - vo / a) + 0.5 * part[3] / a;
       const double dr[3] = {mv.rn[0] - mv.r[0], mv.rn[1] - mv.r[1], mv.rn[2] - mv.r[2]};
       const double Ddot = sm.st[0] * dr[0] + sm.st[1] * dr[1] + sm.st[2] * dr[2];
       const double dd = dr[0] * dr[0] + dr[1] * dr[1] + dr[2] * dr[2];
@@ -941,11 +950,18 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
     ColSum<PM> cs;
     cs.zero();
     int i = g;
-    for (; i + NG < nv; i += 2 * NG) {
-      R v[2][3], c[2];
-      cand_pt(lst[1 + i], v[0], c[0]);
-      cand_pt(lst[1 + i + NG], v[1], c[1]);
-      p2l_sum<GS, PM, R, 2>(lane, cols, v, c, cs);
+    for (; i + NG < nv; i += 4 * NG) {  // up to four at a time; a missing point is a zero charge
+      R v[4][3], c[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (i + k * NG < nv) {
+          cand_pt(lst[1 + i + k * NG], v[k], c[k]);
+        } else {
+          v[k][0] = R(1);
+          v[k][1] = v[k][2] = c[k] = R(0);
+        }
+      }
+      p2l_sum<GS, PM, R, 4>(lane, cols, v, c, cs);
     }
     if (i < nv) {
       R v[1][3], c[1];
@@ -1067,7 +1083,8 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     for (int k = 0; k < 3; ++k) v[k] = (R)fma(x[k], ch.inv_h[l], -((s3[k] + n * w[k]) + 0.5));
     c = (R)(side ? mv.q : -mv.q);
   };
-  // the terms of every candidate in mask m, two at a time
+  // the terms of every candidate in mask m, two at a time (four at a time
+  // measured slower on one wavefront per SIMD)
   auto coarse_sum = [&](int l, const int s3[3], uint64_t m, ColSum<PM> &cs) __attribute__((always_inline)) {
     while (m) {
       const int c0 = __ffsll((unsigned long long)m) - 1;

@@ -159,11 +159,12 @@ __global__ void k_m2m(const Chain *chains, Tabs tb, int l) {
 // (the FMM initialisation without L2L, Sec. 3.2). The operators T_o do not
 // depend on the level (coefficients are scaled by the cell size), so every
 // target cell of one octant, on any level of any chain, multiplies the same
-// 189 matrices: a batched GEMM on the matrix cores. A tile is up to 64
-// targets of one octant of one chain; a workgroup computes TO output
-// coefficients of its tile. The four wavefronts each own 6 x 2 (TO = 192)
-// or 3 x 2 (TO = 96) 16 x 16 accumulator blocks; inputs are staged through
-// LDS in chunks of 16, double-buffered, the multipoles gathered per target.
+// 189 matrices: a batched GEMM on the matrix cores. A tile is up to
+// M2L_TT targets of one octant of one chain; a workgroup computes TO output
+// coefficients of its tile, so each operator element it stages serves the
+// tile's targets. The four wavefronts each own (TO / 32) x (M2L_TT / 32)
+// 16 x 16 accumulator blocks; inputs are staged through LDS in chunks of
+// 16, double-buffered, the multipoles gathered per target.
 // In FP32 the matrix cores accumulate one offset's product (at most Cs
 // terms per output) and each offset's partial sum is added into an FP64
 // accumulator, so the rounding of the 189-offset sum is FP64's.
@@ -188,7 +189,7 @@ struct Mfma<float> {
 };
 
 constexpr int M2L_NT = 256;  // threads of the M2L kernel
-constexpr int M2L_TT = 64;   // targets per tile
+constexpr int M2L_TT = 64;   // targets per tile (128 measured slower: fewer workgroups)
 constexpr int M2L_KC = 16;   // inputs per staged chunk
 
 // target t of an octant's list (levels 2, 3, ... in turn, 8^(l-2) targets
@@ -219,11 +220,13 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
   const int j0 = blockIdx.y * TO;
   const int C = tb.C, Cs = tb.Cs;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int ro = (w >> 1) * (TO / 2), co = (w & 1) * 32;
+  constexpr int CB = M2L_TT / 32;  // column blocks of a wavefront
+  constexpr int BR = M2L_KC * M2L_TT / M2L_NT;  // inputs per thread and chunk
+  const int ro = (w >> 1) * (TO / 2), co = (w & 1) * (M2L_TT / 2);
   // loader roles: A rows t/16 of the chunk, 4 outputs at (t%16)*4 + 64 r;
-  // B target t%64, inputs (t/64)*4 .. +3 of the chunk
+  // B target t % M2L_TT, inputs BR (t / M2L_TT) .. + BR - 1 of the chunk
   const int arow = t >> 4, acol = (t & 15) * 4;
-  const int bt = t & 63, brow = (t >> 6) * 4;
+  const int bt = t % M2L_TT, brow = (t / M2L_TT) * BR;
   const bool bvalid = bt < count;
   int bc[3] = {0, 0, 0}, bn = 1;
   const double *bsrc = nullptr;
@@ -235,7 +238,7 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
   constexpr int AR = (TO + 63) / 64;
   const int nq = (C + M2L_KC - 1) / M2L_KC;
   const int total = 189 * nq;
-  T ra[AR][4], rb[4];
+  T ra[AR][4], rb[BR];
   auto fetch = [&](int it) {
     const int k = it / nq, s0 = (it - k * nq) * M2L_KC;
     const int id = tb.il_id[oc * 189 + k];
@@ -255,10 +258,10 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
       const int x = imod(bx, bn), y = imod(by, bn), z = imod(bz, bn);
       const double *pb = bsrc + (size_t)lin3(bn, x, y, z) * Cs + s0 + brow;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) rb[e] = (T)pb[e];
+      for (int e = 0; e < BR; ++e) rb[e] = (T)pb[e];
     } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) rb[e] = (T)0;
+      for (int e = 0; e < BR; ++e) rb[e] = (T)0;
     }
   };
   auto stash = [&](int buf) {
@@ -270,20 +273,20 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
         for (int e = 0; e < 4; ++e) As[buf][arow][col + e] = ra[r][e];
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) Bs[buf][brow + e][bt] = rb[e];
+    for (int e = 0; e < BR; ++e) Bs[buf][brow + e][bt] = rb[e];
   };
-  typename MF::acc_t acc[RB][2];
+  typename MF::acc_t acc[RB][CB];
   constexpr bool split = sizeof(T) == 4;
-  double accd[split ? RB : 1][2][4];
+  double accd[split ? RB : 1][CB][4];
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (typename MF::acc_t){0, 0, 0, 0};
+    for (int j = 0; j < CB; ++j) acc[i][j] = (typename MF::acc_t){0, 0, 0, 0};
   if constexpr (split)
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < CB; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) accd[i][j][v] = 0.0;
   fetch(0);
@@ -295,12 +298,14 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
 #pragma unroll
     for (int k4 = 0; k4 < M2L_KC; k4 += 4) {
       const int kr = k4 + (lane >> 4);
-      const T b0 = Bs[buf][kr][co + (lane & 15)], b1 = Bs[buf][kr][co + 16 + (lane & 15)];
+      T b[CB];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) b[j] = Bs[buf][kr][co + 16 * j + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const T a = As[buf][kr][ro + 16 * i + (lane & 15)];
-        acc[i][0] = MF::mma(a, b0, acc[i][0]);
-        acc[i][1] = MF::mma(a, b1, acc[i][1]);
+#pragma unroll
+        for (int j = 0; j < CB; ++j) acc[i][j] = MF::mma(a, b[j], acc[i][j]);
       }
     }
     if constexpr (split) {
@@ -308,7 +313,7 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
 #pragma unroll
         for (int i = 0; i < RB; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < CB; ++j) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) accd[i][j][v] += (double)acc[i][j][v];
             acc[i][j] = (typename MF::acc_t){0, 0, 0, 0};
@@ -320,7 +325,7 @@ __global__ void __launch_bounds__(M2L_NT) k_m2l(const Chain *chains, Tabs tb, co
   }
   // store: lane holds, per block, target co + 16 j + lane%16 and rows MF::row
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < CB; ++j) {
     const int tt = co + 16 * j + (lane & 15);
     if (tt >= count) continue;
     int c[3];
