@@ -712,11 +712,24 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
       bool ok = spin_until_reached(mvseq, num, SPIN_LIMIT);
       s_flag = ok ? 0 : 1;
       if (ok) {
+        // ordered after the number by the fence: the stop flag, the
+        // decision word and the move itself, requested together
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (__hip_atomic_load(glb(stop), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) s_flag = 2;
-        // a move already decided rejected (its decision, or a later one, is out) is skipped
+        const unsigned sp = ld_relaxed(stop);
         const unsigned d = ld_relaxed(dec);
+        const auto slot = glb(mb) + 8 * (num & 3);
+        double m[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m[k] = slot[k];
+        if (sp) s_flag = 2;
+        // a move already decided rejected (its decision, or a later one, is out) is skipped
         s_skip = (d >> 1) > num || ((d >> 1) == num && !(d & 1u));
+        mv.idx = (int)m[0];
+        mv.q = m[1];
+        for (int k = 0; k < 3; ++k) {
+          mv.r[k] = m[2 + k];
+          mv.rn[k] = m[5 + k];
+        }
       }
     }
     __syncthreads();
@@ -748,19 +761,6 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
       }
       confirmed = last_acc;
     }
-    if (t == 0) {
-      const auto slot = glb(mb) + 8 * (num & 3);
-      double m[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) m[k] = slot[k];
-      mv.idx = (int)m[0];
-      mv.q = m[1];
-      for (int k = 0; k < 3; ++k) {
-        mv.r[k] = m[2 + k];
-        mv.rn[k] = m[5 + k];
-      }
-    }
-    __syncthreads();
     locate_move_par(ch, mv);
     __syncthreads();
     // speculation: the updated rows of every own block, in LDS
@@ -776,13 +776,13 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
       uint64_t t0 = __builtin_amdgcn_s_memrealtime();
       int res = 0;  // 0 rejected, 1 accepted, 2 time-out, 3 stopped
       while (true) {
-        const unsigned d = ld_relaxed(dec);
+        const unsigned d = ld_relaxed(dec), sp = ld_relaxed(stop);  // one round trip
         if ((d >> 1) == num) {
           res = (int)(d & 1u);
           break;
         }
         if ((d >> 1) > num) break;
-        if (ld_relaxed(stop)) {
+        if (sp) {
           res = 3;
           break;
         }
