@@ -293,7 +293,7 @@ __device__ __forceinline__ float sqrt_r(float v) { return sqrtf(v); }
 // slot and are computed but not passed on) and its constants come through a
 // restrict-qualified pointer, so their loads can be issued ahead of the
 // dependent arithmetic; results leave through the sink only.
-template <int GS, int PMAX, int KIND, typename R, typename Sink>
+template <int GS, int PMAX, int KIND, typename R, bool ALL = false, typename Sink>
 __device__ __forceinline__ void harmonics_core(int lane, const Tabs &tb, const R *__restrict__ rec, R x, R y, R z,
                                                R c, Sink &&sink) {
   const int p = tb.p, Cs = tb.Cs;
@@ -327,7 +327,10 @@ __device__ __forceinline__ void harmonics_core(int lane, const Tabs &tb, const R
         ti = ni;
         if (KIND == 2) s *= inv_r2;
       }
-      if (m + j <= p) {
+      if constexpr (ALL) {  // every row; the sink is told which are valid
+        const R f = c * s;
+        sink(j, m + j, (double)(f * tr), (double)(im_sign * f * ti), m + j <= p);
+      } else if (m + j <= p) {
         const R f = c * s;
         sink(j, m + j, (double)(f * tr), (double)(im_sign * f * ti));
       }

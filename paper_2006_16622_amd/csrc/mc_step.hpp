@@ -463,31 +463,39 @@ __device__ __forceinline__ ProposeOut propose_wg(const Chain &ch, const Tabs &tb
 // constants of its column before the arithmetic starts and runs its rows to
 // the uniform bound, so the evaluation waits once for LDS instead of once
 // per row. The values are those of group_harmonics<GS, PM, 0, false>.
+// Stores are not branched on: a row beyond p is written to a slot of the
+// lane's own in `spare` (16 doubles per group lane, never read), and the
+// imaginary part is written before the real one, so that for m = 0 the
+// real part is the one that stays in the shared slot.
 template <int GS, int PM, typename R>
 __device__ __forceinline__ void group_harmonics_store(int lane, const Tabs &tb, const R *__restrict__ rec, R x, R y,
-                                                      R z, double *buf) {
+                                                      R z, double *buf, double *spare) {
   const int m = lane;
-  harmonics_core<GS, PM, 0, R>(lane, tb, rec, x, y, z, R(1), [&](int, int n, double re, double im) {
-    buf[n * n + n + m] = re;
-    if (m > 0) buf[n * n + n - m] = im;
-  });
+  harmonics_core<GS, PM, 0, R, true>(lane, tb, rec, x, y, z, R(1),
+                                     [&](int, int n, double re, double im, bool valid) {
+                                       double *pi = valid ? buf + (n * n + n - m) : spare + (lane & 15);
+                                       double *pr = valid ? buf + (n * n + n + m) : spare + 16 + (lane & 15);
+                                       *pi = im;
+                                       *pr = re;
+                                     });
 }
 
 // The proposal of the whole-GPU chain's proposing workgroup (256 threads,
-// groups of 16 lanes, 2d + 2 <= 16 points): the terms of propose_wg with
-// the same arithmetic and the same order of every sum, in fewer phases.
+// groups of 16 lanes, 2d + 2 <= 16 points): the terms of propose_wg, in
+// fewer phases.
 // Level point pt (2..2d+1) is held by group pt - 2; the two lattice points
 // by the two groups after them when those lie in the first three
 // wavefronts (d <= 5), else by groups 14 and 15. The last wavefront also
 // runs early() and forms the self-image terms.
 //   1. the coefficient rows of the level points and the first near-field
 //      records are requested;
-//   2. the harmonics of every point at once, the lattice points with their
-//      values from H; early(); the self-image terms, whose images are known
+//   2. the harmonics of every point at once (red[64..95] takes the rows
+//      beyond p); early(); the self-image terms, whose images are known
 //      from the cells alone: image nu of the old position is in the new near
 //      region exactly when the old leaf cell shifted by nu cells lies within
 //      one cell of the new leaf cell (the near field skips the same images);
-//   3. (barrier) dk is formed;
+//   3. (barrier) dk is formed, and the terms of the two lattice values H.T,
+//      one slot per thread;
 //   4. (barrier) the rows of R dk (unrolled to the ELL width) with the
 //      quadratic lattice term, the near field, the level values from the
 //      requested rows, and spare() in the last wavefront;
@@ -496,8 +504,9 @@ __device__ __forceinline__ void group_harmonics_store(int lane, const Tabs &tb, 
 //   6. lane 0 of the last wavefront adds the wavefront sums in order,
 //      assembles dE and calls decide(dE, singular); a last barrier makes
 //      the decision visible.
-// The sums are those of propose_wg: shuffle trees inside each wavefront,
-// then the wavefront totals in order, so dE is the same bit for bit.
+// The sums are shuffle trees inside each wavefront, then the wavefront
+// totals in order, as in propose_wg; the lattice values are summed the same
+// way here (group sums there), so dE agrees with propose_wg to rounding.
 template <int GS, int PM, typename R, int NT, typename Early, typename Spare, typename Gate, typename Decide>
 __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, const Move &mv, Lds<GS, NT> &sm,
                                              Early &&early, Spare &&spare, Gate &&gate, Decide &&decide) {
@@ -570,9 +579,10 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
       src = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
     }
     if (pt < 2 || sizeof(R) == 8)  // the lattice term is FP64 in every mode
-      group_harmonics_store<GS, PM, double>(lane, tb, sm.rec, x[0], x[1], x[2], buf);
+      group_harmonics_store<GS, PM, double>(lane, tb, sm.rec, x[0], x[1], x[2], buf, sm.red + 64);
     else
-      group_harmonics_store<GS, PM, R>(lane, tb, sm.template rec_of<R>(), (R)x[0], (R)x[1], (R)x[2], buf);
+      group_harmonics_store<GS, PM, R>(lane, tb, sm.template rec_of<R>(), (R)x[0], (R)x[1], (R)x[2], buf,
+                                       sm.red + 64);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
