@@ -589,9 +589,10 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
   auto dot = [&](const double lv[NJ]) __attribute__((always_inline)) {
     double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      int s2 = lane + j * GS;
-      if (s2 < C) acc += lv[j] * sm.wl2p[s2] * buf[s2];
+    for (int j = 0; j < NJ; ++j) {  // loads at a valid slot, the term selected: no branch
+      const int s2 = lane + j * GS, sc = s2 < C ? s2 : C - 1;
+      const double term = lv[j] * sm.wl2p[sc] * buf[sc];
+      acc += s2 < C ? term : 0.0;
     }
     acc = group_sum<GS>(acc);
     if (lane == 0) sm.vals[pt] = acc / hh;
