@@ -65,11 +65,11 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "81379cbd5c076f439ff784e4f1da5017f533236052aed9517d2462924333bde5",
-    "fetch_bytes_per_step": 760097.0,
+    "src_sha256": "68e64d360d388928e06386775cb318e30a1464fae51dca688149745e22a8c6d1",
+    "fetch_bytes_per_step": 770910.0,
     "write_bytes_per_step": 438489.0,
-    "batched_fetch_bytes_per_step": 209421.0,
-    "batched_write_bytes_per_step": 188500.0,
+    "batched_fetch_bytes_per_step": 209448.0,
+    "batched_write_bytes_per_step": 188501.0,
 }
 
 
