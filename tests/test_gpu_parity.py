@@ -18,6 +18,8 @@ CASES = {
     "n1000_d3_p8": W.small,
     "n64_d1_p4": lambda: W.uniform(64, 1, 4, 0.1, seed=12, key=2),
     "n300_d2_p16": lambda: W.uniform(300, 2, 16, 0.05, seed=13, key=3),
+    # the third 16-lane degree bound (p 13..15): the whole-GPU chain and k_run_chains
+    "n800_d2_p14": lambda: W.uniform(800, 2, 14, 0.05, seed=15, key=5),
     "n2000_d3_p3_ragged": lambda: W.uniform(2002, 3, 3, 0.03, seed=14, key=4),
 }
 
