@@ -872,20 +872,6 @@ __device__ __forceinline__ uint64_t coarse_mask(const Move &mv, int l, const int
   return m;
 }
 
-// add one contribution (candidate bit) of a coarse cell to a group buffer
-template <int GS, int PM, typename R>
-__device__ __forceinline__ void coarse_contrib(const Tabs &tb, const R *rec, const Move &mv, int l,
-                                               const int s[3], int cand, double a, int lane, double *buf) {
-  const int n = 1 << (l - 1);
-  const double h = a / n;
-  const int side = cand / 27, e = cand % 27;
-  const int w[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
-  const double *x = side ? mv.rn : mv.r;
-  double v[3];
-  for (int k = 0; k < 3; ++k) v[k] = (x[k] - ((s[k] + n * w[k]) + 0.5) * h) / h;
-  group_harmonics<GS, PM, 2, true, R>(lane, tb, rec, (R)v[0], (R)v[1], (R)v[2], (R)(side ? mv.q : -mv.q), buf);
-}
-
 // The updated target rows of accept block blk of move mv, formed in LDS
 // without writing the targets: out (NG x Cs doubles) receives the old
 // values read now plus the block's additions, and dst[g] the row that
