@@ -65,7 +65,7 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "5450851c62e6ee6b2c7dfe49c3c36820c859a2983c669c77851bdc425d47ec0e",
+    "src_sha256": "2e0cfd6b95f354c02a8be932723bbc64f6d7e4fddf92622889fe46f636b706cf",
     "fetch_bytes_per_step": 770910.0,
     "write_bytes_per_step": 438489.0,
     "batched_fetch_bytes_per_step": 209448.0,

@@ -1,10 +1,13 @@
 // run_kernels.hpp -- Metropolis-Hastings chains on the device.
 //
-//  * k_run_batched: one workgroup per chain, every chain its own state; the
-//    workgroup proposes, decides and, on accept, walks every update block
-//    itself. No inter-workgroup communication: hundreds of independent
-//    chains of uneven size and depth in one launch (independent chains run
-//    side by side, one of the routes to parallelism named in Sec. 6).
+//  * k_run_chains (16-lane groups) and k_run_batched (32-lane groups, and
+//    the multipole variant): one workgroup per chain, every chain its own
+//    state; the workgroup proposes, decides and, on accept, walks every
+//    update block itself. No inter-workgroup communication: hundreds of
+//    independent chains of uneven size and depth in one launch (independent
+//    chains run side by side, one of the routes to parallelism named in
+//    Sec. 6). k_run_chains runs the loop of k_run_single's workgroup 0
+//    (run_chain_wg) without helpers.
 //  * k_run_single: one chain on many workgroups (cooperative launch, all
 //    co-resident). Workgroup 0 proposes, decides and keeps the bookkeeping;
 //    it posts every move in a mailbox, and the update blocks of Alg. L.2,
@@ -16,9 +19,9 @@
 //
 // A step draws (idx, delta, u) from Philox4x64-10 (key = (seed, chain),
 // counter = (t, 0|1, 0, 0)) or reads them from fixed lists; the move is
-// accepted iff u < exp(-beta dE) and it is not singular. The draw of step
-// t+1 and the record of its particle are fetched by an idle wavefront while
-// step t is being proposed.
+// accepted iff u < exp(-beta dE) and it is not singular. The next move is
+// drawn, located and (for the helpers) posted by the last wavefront while
+// the current one is being proposed.
 #pragma once
 
 #include "mp_step.hpp"
