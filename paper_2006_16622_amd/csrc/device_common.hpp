@@ -84,6 +84,7 @@ struct Lds {
   int *lat_col;                // W Cs (when resident)
   double *gbuf;                // NG Cs: one buffer per group
   double *latO, *latN, *dk;    // Cs each
+  double *p2lg, *p2la;         // Cs each: P2L column constants g_j and alpha_j
   double *red;                 // NT
   double *vals;                // 32
   double4 *stash;              // 2: records kept by the proposal for the bookkeeping
@@ -101,7 +102,9 @@ struct Lds {
     latO = gbuf + (size_t)NG * Cs;
     latN = latO + Cs;
     dk = latN + Cs;
-    red = dk + Cs;
+    p2lg = dk + Cs;
+    p2la = p2lg + Cs;
+    red = p2la + Cs;
     vals = red + NT;
     stash = (double4 *)(vals + 32);
     ints = (int *)(stash + 2);
@@ -111,7 +114,7 @@ struct Lds {
     dstp = (double **)(il_off + 8 * 189 * 3);
   }
   __host__ __device__ static size_t bytes(int Cs, int ellw) {
-    return sizeof(double) * ((size_t)(NG + 12 + ellw) * Cs + 8 + NT + 32 + 8) + 4 * (384 + (size_t)ellw * Cs) +
+    return sizeof(double) * ((size_t)(NG + 14 + ellw) * Cs + 8 + NT + 32 + 8) + 4 * (384 + (size_t)ellw * Cs) +
            4 * 3 * (size_t)Cs + 8 * 189 * 3 + sizeof(double *) * NG;
   }
   // recurrence constants in the evaluation type
@@ -449,9 +452,10 @@ __device__ __forceinline__ void flush_cols(int lane, const Tabs &tb, const ColSu
 //   xi = (x + i y) / r^2,  S_0 = 1,  S_1 = z / r^2,
 //   S_j = (z / r^2) S_{j-1} + g_j S_{j-2} / r^2,
 //   g_j = -B(n,m) / (A(n,m) A(n-1,m)),  alpha_j = c_m A(m+1,m) ... A(n,m),
-// (S_j = P_n / (alpha_j r^(2j))). Lane m keeps g_j in registers for a run of
-// evaluations and sums G S_j over the points; alpha_j is applied once, when
-// the sums are written out. Rows beyond p have g_j = 0 and are never
+// (S_j = P_n / (alpha_j r^(2j))). Both constants are tabulated once per
+// workgroup; lane m keeps g_j in registers for a run of evaluations and sums
+// G S_j over the points; alpha_j is applied once, when the sums are written
+// out. Rows beyond p have g_j = 0 and are never
 // written; neither are lanes beyond p.
 __device__ __forceinline__ double rsqrt_nr(double v) {
   double y = __builtin_amdgcn_rsq(v);
@@ -473,17 +477,29 @@ struct P2LCols {
   R g[PMAX + 1];  // g[j], j >= 2
 };
 
+// the constants of column m (one thread per column; rec: the recurrence
+// constants in global memory): g_j and alpha_j at slot (m + j, m)
+__device__ __forceinline__ void fill_p2l_cols(int m, const Tabs &tb, double *g, double *alpha) {
+  const int p = tb.p, Cs = tb.Cs;
+  const double *rec = tb.rec;
+  if (m > p) return;
+  double a = rec[2 * Cs + m];
+  for (int n = m; n <= p; ++n) {
+    const int s = n * n + n + m, s1 = (n - 1) * (n - 1) + (n - 1) + m;
+    if (n > m) a *= rec[s];
+    alpha[s] = a;
+    g[s] = n >= m + 2 ? -rec[Cs + s] / (rec[s] * rec[s1]) : 0.0;
+  }
+}
+
 template <int PMAX, typename R>
-__device__ __forceinline__ void load_p2l_cols(int lane, const Tabs &tb, const double *rec, P2LCols<PMAX, R> &cols) {
-  const int p = tb.p, Cs = tb.Cs, m = lane;
+__device__ __forceinline__ void load_p2l_cols(int lane, const Tabs &tb, const double *g, P2LCols<PMAX, R> &cols) {
+  const int p = tb.p, m = lane;
 #pragma unroll
   for (int j = 0; j <= PMAX; ++j) {
     const int n = m + j;
     cols.g[j] = R(0);
-    if (j >= 2 && n <= p) {
-      const int s = n * n + n + m, s1 = (n - 1) * (n - 1) + (n - 1) + m;
-      cols.g[j] = (R)(-rec[Cs + s] / (rec[s] * rec[s1]));
-    }
+    if (j >= 2 && n <= p) cols.g[j] = (R)g[n * n + n + m];
   }
 }
 
@@ -534,18 +550,17 @@ __device__ __forceinline__ void p2l_sum(int lane, const P2LCols<PMAX, R> &cols, 
 
 // write a group's P2L column sums, times alpha_j, into the real-layout buffer
 template <int PMAX, typename P>
-__device__ __forceinline__ void flush_p2l(int lane, const Tabs &tb, const double *rec, const ColSum<PMAX> &acc, P buf) {
-  const int p = tb.p, Cs = tb.Cs, m = lane;
+__device__ __forceinline__ void flush_p2l(int lane, const Tabs &tb, const double *alpha, const ColSum<PMAX> &acc, P buf) {
+  const int p = tb.p, m = lane;
   if (m > p) return;
-  double alpha = rec[2 * Cs + m];
 #pragma unroll
   for (int j = 0; j <= PMAX; ++j) {
     const int n = m + j;
     if (n <= p) {
       const int sp = n * n + n + m;
-      if (j > 0) alpha *= rec[sp];
-      buf[sp] = alpha * acc.re[j];
-      if (m > 0) buf[n * n + n - m] = alpha * acc.im[j];
+      const double a = alpha[sp];
+      buf[sp] = a * acc.re[j];
+      if (m > 0) buf[n * n + n - m] = a * acc.im[j];
     }
   }
 }

@@ -81,6 +81,7 @@ __device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<G
       sm.lat_val[i] = tb.lat_val[i];
       sm.lat_col[i] = tb.lat_col[i];
     }
+  if (threadIdx.x >= NT - 32) fill_p2l_cols(threadIdx.x - (NT - 32), tb, sm.p2lg, sm.p2la);
   if (state && threadIdx.x < 3) sm.st[threadIdx.x] = ch.dip[threadIdx.x];
   if (state && threadIdx.x == 3) sm.st[3] = ch.U[0];
   // the image mask of the first proposal starts empty (each proposal clears
@@ -936,7 +937,7 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
     // time) and writes its column sums once
     const int nv = lst[0];
     P2LCols<PM, R> cols;
-    load_p2l_cols<PM, R>(lane, tb, sm.rec, cols);
+    load_p2l_cols<PM, R>(lane, tb, sm.p2lg, cols);
     auto cand_pt = [&](int cand, R v[3], R &c) __attribute__((always_inline)) {
       const int side = cand / 27, e = cand % 27;
       const int w[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
@@ -965,7 +966,7 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
       cand_pt(lst[1 + i], v[0], c[0]);
       p2l_sum<GS, PM, R, 1>(lane, cols, v, c, cs);
     }
-    flush_p2l<PM>(lane, tb, sm.rec, cs, acc + (size_t)g * Cs);
+    flush_p2l<PM>(lane, tb, sm.p2la, cs, acc + (size_t)g * Cs);
     __syncthreads();
     for (int k = t; k < C; k += NT) {
       double sum = 0.0;
@@ -994,7 +995,7 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
   }
   // the one or two contributions are summed in registers, then written once
   P2LCols<PM, R> cols;
-  load_p2l_cols<PM, R>(lane, tb, sm.rec, cols);
+  load_p2l_cols<PM, R>(lane, tb, sm.p2lg, cols);
   ColSum<PM> cs;
   cs.zero();
   if (it.two) {
@@ -1006,7 +1007,7 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
     const R c[1] = {(R)it.q0};
     p2l_sum<GS, PM, R, 1>(lane, cols, v, c, cs);
   }
-  flush_p2l<PM>(lane, tb, sm.rec, cs, buf);
+  flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
@@ -1069,7 +1070,7 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
   const int L = ch.L;
   double *buf = sm.gbuf + (size_t)g * Cs;
   P2LCols<PM, R> cols;
-  load_p2l_cols<PM, R>(lane, tb, sm.rec, cols);
+  load_p2l_cols<PM, R>(lane, tb, sm.p2lg, cols);
   // the point of candidate `cand` (side 27 side + image) of stored cell s3
   // of coarse level l, in cell units from the image's centre
   auto coarse_pt = [&](int l, const int s3[3], int cand, R v[3], R &c) __attribute__((always_inline)) {
@@ -1102,7 +1103,7 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
   };
   // row := old + sums (old read slot by slot before the sums were formed)
   auto finish_row = [&](gptr<double> dst, const double old[NJ], const ColSum<PM> &cs) __attribute__((always_inline)) {
-    flush_p2l<PM>(lane, tb, sm.rec, cs, buf);
+    flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
@@ -1122,7 +1123,7 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     ColSum<PM> cs;
     cs.zero();
     coarse_sum(2, s3, m, cs);
-    flush_p2l<PM>(lane, tb, sm.rec, cs, buf);
+    flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
   }
   __syncthreads();
   for (int i = t; i < 8 * C; i += NT) {
