@@ -65,11 +65,11 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "2e0cfd6b95f354c02a8be932723bbc64f6d7e4fddf92622889fe46f636b706cf",
-    "fetch_bytes_per_step": 770910.0,
+    "src_sha256": "9bf4b14fd4ce3c84cc074b327c6643c4188a05f4d5aa1fcc70d16f3466d24f13",
+    "fetch_bytes_per_step": 785216.0,
     "write_bytes_per_step": 438489.0,
-    "batched_fetch_bytes_per_step": 209448.0,
-    "batched_write_bytes_per_step": 188501.0,
+    "batched_fetch_bytes_per_step": 209417.0,
+    "batched_write_bytes_per_step": 188499.0,
 }
 
 
