@@ -1101,15 +1101,20 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
       }
     }
   };
-  // row := old + sums (old read slot by slot before the sums were formed)
+  // row := old + sums (old read slot by slot before the sums were formed,
+  // slots >= C as slot C - 1). No store is branched on: a lane whose slot
+  // lies beyond C stores slot C - 1 again, with the same value. (With the
+  // stores under a branch the wavefront could not count its outstanding
+  // loads and stores, and waited for this row's stores before it requested
+  // the next target's row.)
   auto finish_row = [&](gptr<double> dst, const double old[NJ], const ColSum<PM> &cs) __attribute__((always_inline)) {
     flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      int k = lane + j * GS;
-      if (k < C) dst[k] = old[j] + buf[k];
+      const int k = min(lane + j * GS, C - 1);
+      dst[k] = old[j] + buf[k];
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1126,12 +1131,24 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
   }
   __syncthreads();
-  for (int i = t; i < 8 * C; i += NT) {
-    const int cell = i / C, k = i % C;
-    double sum = 0.0;
-    for (int part = 0; part < SPLIT2; ++part) sum += sm.gbuf[(size_t)(cell + 8 * part) * Cs + k];
-    const auto dst = glb(ch.Ld) + ch.ld_off[2] + (size_t)cell * Cs;
-    dst[k] += sum;
+  {
+    // the 8 rows: every value requested before any is stored (index i
+    // beyond 8 C takes the last slot again, with the same value)
+    constexpr int NR2 = (8 * (PM + 1) * (PM + 1) + NT - 1) / NT;
+    const auto dst = glb(ch.Ld) + ch.ld_off[2];
+    double old2[NR2];
+#pragma unroll
+    for (int r = 0; r < NR2; ++r) {
+      const int i = min(t + r * NT, 8 * C - 1), cell = i / C, k = i % C;
+      old2[r] = dst[(size_t)cell * Cs + k];
+    }
+#pragma unroll
+    for (int r = 0; r < NR2; ++r) {
+      const int i = min(t + r * NT, 8 * C - 1), cell = i / C, k = i % C;
+      double sum = 0.0;
+      for (int part = 0; part < SPLIT2; ++part) sum += sm.gbuf[(size_t)(cell + 8 * part) * Cs + k];
+      dst[(size_t)cell * Cs + k] = old2[r] + sum;
+    }
   }
   __syncthreads();
   // ---- level 3
@@ -1141,7 +1158,7 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
       const auto dst = glb(ch.Ld) + ch.ld_off[3] + (size_t)cell * Cs;
       double old[NJ];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) old[j] = dst[min(lane + j * GS, Cs - 1)];  // slots >= C are not used
+      for (int j = 0; j < NJ; ++j) old[j] = dst[min(lane + j * GS, C - 1)];
       const uint64_t m = coarse_mask<GS>(mv, 3, s3, lane, ch.free_space);
       ColSum<PM> cs;
       cs.zero();
@@ -1157,7 +1174,7 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     const auto dst = glb(it.dst);
     double old[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) old[j] = dst[min(lane + j * GS, Cs - 1)];
+    for (int j = 0; j < NJ; ++j) old[j] = dst[min(lane + j * GS, C - 1)];
     ColSum<PM> cs;
     cs.zero();
     if (it.two) {
