@@ -65,11 +65,11 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "9bf4b14fd4ce3c84cc074b327c6643c4188a05f4d5aa1fcc70d16f3466d24f13",
-    "fetch_bytes_per_step": 785216.0,
+    "src_sha256": "dd478784e457a567cba455127840c5da4255813c5043feead05a292dcb6edb9e",
+    "fetch_bytes_per_step": 782952.0,
     "write_bytes_per_step": 438489.0,
-    "batched_fetch_bytes_per_step": 209417.0,
-    "batched_write_bytes_per_step": 188499.0,
+    "batched_fetch_bytes_per_step": 209736.0,
+    "batched_write_bytes_per_step": 188502.0,
 }
 
 
