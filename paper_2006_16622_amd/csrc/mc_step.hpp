@@ -1069,6 +1069,10 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
   const int t = threadIdx.x, g = t / GS, lane = t % GS;
   const int L = ch.L;
   double *buf = sm.gbuf + (size_t)g * Cs;
+  // rows stored without branches (finish_row) up to the p <= 12 variant; the
+  // larger variants keep branched stores, whose addresses take no registers
+  // of their own (the unbranched form spilled there and slowed the proposal)
+  constexpr bool UNBRANCHED = PM <= 12;
   P2LCols<PM, R> cols;
   load_p2l_cols<PM, R>(lane, tb, sm.p2lg, cols);
   // the point of candidate `cand` (side 27 side + image) of stored cell s3
@@ -1102,19 +1106,24 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     }
   };
   // row := old + sums (old read slot by slot before the sums were formed,
-  // slots >= C as slot C - 1). No store is branched on: a lane whose slot
-  // lies beyond C stores slot C - 1 again, with the same value. (With the
-  // stores under a branch the wavefront could not count its outstanding
-  // loads and stores, and waited for this row's stores before it requested
-  // the next target's row.)
+  // slots >= C as slot C - 1). UNBRANCHED: no store is branched on, a lane
+  // whose slot lies beyond C stores slot C - 1 again, with the same value.
+  // (With the stores under a branch the wavefront cannot count its
+  // outstanding loads and stores, and waits for this row's stores before it
+  // requests the next target's row.)
   auto finish_row = [&](gptr<double> dst, const double old[NJ], const ColSum<PM> &cs) __attribute__((always_inline)) {
     flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int k = min(lane + j * GS, C - 1);
-      dst[k] = old[j] + buf[k];
+      if constexpr (UNBRANCHED) {
+        const int k = min(lane + j * GS, C - 1);
+        dst[k] = old[j] + buf[k];
+      } else {
+        const int k = lane + j * GS;
+        if (k < C) dst[k] = old[j] + buf[k];
+      }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1131,7 +1140,15 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
   }
   __syncthreads();
-  {
+  if constexpr (!UNBRANCHED) {
+    for (int i = t; i < 8 * C; i += NT) {
+      const int cell = i / C, k = i % C;
+      double sum = 0.0;
+      for (int part = 0; part < SPLIT2; ++part) sum += sm.gbuf[(size_t)(cell + 8 * part) * Cs + k];
+      const auto dst = glb(ch.Ld) + ch.ld_off[2] + (size_t)cell * Cs;
+      dst[k] += sum;
+    }
+  } else {
     // the 8 rows: every value requested before any is stored (index i
     // beyond 8 C takes the last slot again, with the same value)
     constexpr int NR2 = (8 * (PM + 1) * (PM + 1) + NT - 1) / NT;
