@@ -65,11 +65,11 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "dd478784e457a567cba455127840c5da4255813c5043feead05a292dcb6edb9e",
-    "fetch_bytes_per_step": 782952.0,
+    "src_sha256": "94e34b5388ca760dac78166a2ae18a4e2973154c2e0bf64290707a69b4642018",
+    "fetch_bytes_per_step": 782740.0,
     "write_bytes_per_step": 438489.0,
-    "batched_fetch_bytes_per_step": 209736.0,
-    "batched_write_bytes_per_step": 188502.0,
+    "batched_fetch_bytes_per_step": 209732.0,
+    "batched_write_bytes_per_step": 188497.0,
 }
 
 
