@@ -75,7 +75,7 @@ struct Lds {
   static constexpr int NG = NT / GS;
   double *rec;                 // 3 Cs: recurrence constants
   float *rec32;                // 3 Cs: the same in FP32 (mixed precision evaluation)
-  int8_t *il_off;              // 8 * 189 * 3: interaction-list offsets per octant
+  int *il32;                   // 8 * 189: interaction-list offsets per octant, one word each
   double **dstp;               // NG: destination rows of an accept block's groups
   double *wl2p, *wdot, *sgnc;  // Cs each
   double *H, *K;               // Cs each: chain state
@@ -110,12 +110,12 @@ struct Lds {
     ints = (int *)(stash + 2);
     lat_col = ints + 384;
     rec32 = (float *)(lat_col + (size_t)ellw * Cs);
-    il_off = (int8_t *)(rec32 + 3 * (size_t)Cs);
-    dstp = (double **)(il_off + 8 * 189 * 3);
+    il32 = (int *)(rec32 + 3 * (size_t)Cs);
+    dstp = (double **)(il32 + 8 * 189);
   }
   __host__ __device__ static size_t bytes(int Cs, int ellw) {
     return sizeof(double) * ((size_t)(NG + 14 + ellw) * Cs + 8 + NT + 32 + 8) + 4 * (384 + (size_t)ellw * Cs) +
-           4 * 3 * (size_t)Cs + 8 * 189 * 3 + sizeof(double *) * NG;
+           4 * 3 * (size_t)Cs + 4 * 8 * 189 + sizeof(double *) * NG;
   }
   // recurrence constants in the evaluation type
   template <typename R>
@@ -128,6 +128,23 @@ struct Lds {
 };
 
 __device__ __forceinline__ int cslot(int n, int m) { return n * n + n + m; }
+
+// the three signed byte offsets of an interaction-list entry, kept in LDS as
+// one word (x in the low byte), so that an entry is a single LDS read
+__device__ __forceinline__ int il_pack(const int8_t *o) {
+  return (int)(uint8_t)o[0] | ((int)(uint8_t)o[1] << 8) | ((int)(uint8_t)o[2] << 16);
+}
+__device__ __forceinline__ void il_unpack(int w, int o[3]) {
+  o[0] = (w << 24) >> 24;
+  o[1] = (w << 16) >> 24;
+  o[2] = (w << 8) >> 24;
+}
+// entry i of an interaction-list table: the packed LDS copy, or the byte
+// table of the constant tables in global memory
+__device__ __forceinline__ void il_entry(const int *il32, int i, int o[3]) { il_unpack(il32[i], o); }
+__device__ __forceinline__ void il_entry(const int8_t *il, int i, int o[3]) {
+  for (int k = 0; k < 3; ++k) o[k] = il[3 * i + k];
+}
 
 // Global-memory view of a workspace pointer. The chain's pointers reach the
 // kernels through LDS, so the compiler no longer knows they address global

@@ -66,7 +66,7 @@ __device__ __forceinline__ void stage_lds(const Chain &ch, const Tabs &tb, Lds<G
     sm.rec[i] = tb.rec[i];
     sm.rec32[i] = (float)tb.rec[i];
   }
-  for (int i = threadIdx.x; i < 8 * 189 * 3; i += NT) sm.il_off[i] = tb.il_off[i];
+  for (int i = threadIdx.x; i < 8 * 189; i += NT) sm.il32[i] = il_pack(tb.il_off + 3 * i);
   for (int i = threadIdx.x; i < Cs; i += NT) {
     sm.wl2p[i] = tb.wl2p[i];
     sm.wdot[i] = tb.wdot[i];
@@ -807,18 +807,43 @@ struct FineItem {
   double q0, q1;
 };
 
-__device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, const int8_t *il_off, const Move &mv,
-                                              int l, int item) {
+// the quantities of fine level l that every item of a move shares, read
+// once per level instead of once per item
+struct FineLevel {
+  int n;
+  double inv_h;
+  int c0[3], c1[3];  // cells of r and r'
+  int oc0, oc1;      // their octants
+  double *rows;      // the level's local expansions
+};
+
+__device__ __forceinline__ FineLevel fine_level(const Chain &ch, const Move &mv, int l) {
+  FineLevel fl;
+  fl.n = 1 << (l - 1);
+  fl.inv_h = ch.inv_h[l];
+  for (int k = 0; k < 3; ++k) {
+    fl.c0[k] = mv.c0[l][k];
+    fl.c1[k] = mv.c1[l][k];
+  }
+  fl.oc0 = (fl.c0[0] & 1) | ((fl.c0[1] & 1) << 1) | ((fl.c0[2] & 1) << 2);
+  fl.oc1 = (fl.c1[0] & 1) | ((fl.c1[1] & 1) << 1) | ((fl.c1[2] & 1) << 2);
+  fl.rows = ch.Ld + ch.ld_off[l];
+  return fl;
+}
+
+__device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, const int *il32, const Move &mv,
+                                              const FineLevel &fl, int item) {
   FineItem it;
   it.active = 0;
   it.two = 0;
-  const int n = 1 << (l - 1);
-  const double inv_h = ch.inv_h[l];
-  const int side = item / 189, k189 = item % 189;
-  const int *c = side ? mv.c1[l] : mv.c0[l];
-  const int *co = side ? mv.c0[l] : mv.c1[l];
-  const int oc = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
-  const int8_t *o = il_off + (oc * 189 + k189) * 3;
+  const int n = fl.n;
+  const int side = item >= 189, k189 = side ? item - 189 : item;
+  int c[3], co[3], o[3];
+  for (int k = 0; k < 3; ++k) {
+    c[k] = side ? fl.c1[k] : fl.c0[k];
+    co[k] = side ? fl.c0[k] : fl.c1[k];
+  }
+  il_unpack(il32[(side ? fl.oc1 : fl.oc0) * 189 + k189], o);
   int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
   int s[3] = {pmod(b[0], n), pmod(b[1], n), pmod(b[2], n)};
   if (ch.free_space && (b[0] != s[0] || b[1] != s[1] || b[2] != s[2])) return it;  // outside the box
@@ -826,13 +851,13 @@ __device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, c
   const bool other = image_in_il(s, co, n, b_other, ch.free_space);
   if (side == 1 && other) return it;  // owned by the old-side item
   it.active = 1;
-  it.dst = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, s[0], s[1], s[2]) * tb.Cs;
+  it.dst = fl.rows + (size_t)lin3(n, s[0], s[1], s[2]) * tb.Cs;
   const double *x = side ? mv.rn : mv.r;
-  for (int k = 0; k < 3; ++k) it.v0[k] = fma(x[k], inv_h, -(b[k] + 0.5));
+  for (int k = 0; k < 3; ++k) it.v0[k] = fma(x[k], fl.inv_h, -(b[k] + 0.5));
   it.q0 = side ? mv.q : -mv.q;
   if (side == 0 && other) {
     it.two = 1;
-    for (int k = 0; k < 3; ++k) it.v1[k] = fma(mv.rn[k], inv_h, -(b_other[k] + 0.5));
+    for (int k = 0; k < 3; ++k) it.v1[k] = fma(mv.rn[k], fl.inv_h, -(b_other[k] + 0.5));
     it.q1 = mv.q;
   }
   return it;
@@ -982,7 +1007,7 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
   const int item = (b2 % bpl) * NG + g;
   FineItem it;
   it.active = 0;
-  if (l <= L && item < 378) it = fine_item(ch, tb, sm.il_off, mv, l, item);
+  if (l <= L && item < 378) it = fine_item(ch, tb, sm.il32, mv, fine_level(ch, mv, l), item);
   if (lane == 0) dst[g] = it.active ? it.dst : nullptr;
   if (!it.active) return false;
   double *buf = out + (size_t)g * Cs;
@@ -1185,8 +1210,15 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
   }
   // ---- levels >= 4: one or two terms per item's own target
   const int nfine = L >= 4 ? (L - 3) * 378 : 0;
+  int fl_l = 0;  // the level whose shared quantities fl holds
+  FineLevel fl;
   for (int i = g; i < nfine; i += NG) {
-    const FineItem it = fine_item(ch, tb, sm.il_off, mv, 4 + i / 378, i % 378);
+    const int l = 4 + i / 378;
+    if (l != fl_l) {
+      fl = fine_level(ch, mv, l);
+      fl_l = l;
+    }
+    const FineItem it = fine_item(ch, tb, sm.il32, mv, fl, i - (l - 4) * 378);
     if (!it.active) continue;
     const auto dst = glb(it.dst);
     double old[NJ];

@@ -22,13 +22,14 @@ __host__ __device__ inline int mp_items(int L) { return 378 * (L - 1); }
 // layout: Re at slot (n, m), Im at slot (n, -m)), so that the group sum of
 // the returned lane values is Re sum M_n^m I_n^m = Phi_b(x - R_b), with the
 // weights 1 (m = 0) and 2 (m > 0) of the real form and 1/h of the scaling.
-template <int GS, int PM>
-__device__ __forceinline__ double m2p_cell(const Chain &ch, const Tabs &tb, const double *rec, const int8_t *il_off,
+template <int GS, int PM, typename IL>
+__device__ __forceinline__ double m2p_cell(const Chain &ch, const Tabs &tb, const double *rec, const IL *il,
                                            int l, const int c[3], const double x[3], int k, int lane) {
   const int n = 1 << (l - 1);
   const double h = ch.a / n;
   const int oc = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
-  const int8_t *o = il_off + (oc * 189 + k) * 3;
+  int o[3];
+  il_entry(il, oc * 189 + k, o);
   const int b[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
   // free space: cells outside the box hold nothing (uniform over the group)
   if (ch.free_space && (b[0] < 0 || b[0] >= n || b[1] < 0 || b[1] >= n || b[2] < 0 || b[2] >= n)) return 0.0;
@@ -55,10 +56,10 @@ __device__ __forceinline__ double m2p_cell(const Chain &ch, const Tabs &tb, cons
 // item i of the far field of move mv, with the sign of its side
 // (+ at r' over IL(a'_l), - at r over IL(a_l)), as lane values
 template <int GS, int PM>
-__device__ __forceinline__ double m2p_item(const Chain &ch, const Tabs &tb, const double *rec, const int8_t *il_off,
+__device__ __forceinline__ double m2p_item(const Chain &ch, const Tabs &tb, const double *rec, const int *il32,
                                            const Move &mv, int item, int lane) {
   const int l = 2 + item / 378, rem = item % 378, side = rem / 189, k = rem % 189;
-  const double v = m2p_cell<GS, PM>(ch, tb, rec, il_off, l, side ? mv.c1[l] : mv.c0[l], side ? mv.rn : mv.r, k, lane);
+  const double v = m2p_cell<GS, PM>(ch, tb, rec, il32, l, side ? mv.c1[l] : mv.c0[l], side ? mv.rn : mv.r, k, lane);
   return side ? v : -v;
 }
 
@@ -67,11 +68,11 @@ __device__ __forceinline__ double m2p_item(const Chain &ch, const Tabs &tb, cons
 // order per group)
 template <int GS, int PM>
 __device__ __forceinline__ double m2p_far_part(const Chain &ch, const Tabs &tb, const double *rec,
-                                               const int8_t *il_off, const Move &mv, int first, int stride) {
+                                               const int *il32, const Move &mv, int first, int stride) {
   const int g = threadIdx.x / GS, lane = threadIdx.x % GS;
   const int ni = mp_items(ch.L);
   double acc = 0.0;
-  for (int i = first + g; i < ni; i += stride) acc += m2p_item<GS, PM>(ch, tb, rec, il_off, mv, i, lane);
+  for (int i = first + g; i < ni; i += stride) acc += m2p_item<GS, PM>(ch, tb, rec, il32, mv, i, lane);
   return acc;
 }
 
@@ -84,7 +85,7 @@ __device__ ProposeOut propose_mp_wg(const Chain &ch, const Tabs &tb, const Move 
                                     Spare &&spare) {
   constexpr int NG = NT / GS;
   ProposeOut po = propose_wg<GS, PM, double, false>(ch, tb, mv, sm, spare);
-  double far = m2p_far_part<GS, PM>(ch, tb, sm.rec, sm.il_off, mv, 0, NG);
+  double far = m2p_far_part<GS, PM>(ch, tb, sm.rec, sm.il32, mv, 0, NG);
   far = wg_sum<NT>(far, sm.red);
   po.dE += mv.q * far;
   return po;

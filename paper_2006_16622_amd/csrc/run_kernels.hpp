@@ -938,7 +938,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
         __syncthreads();
       } else {
         // no helpers: the workgroup evaluates every item itself
-        double f = m2p_far_part<GS, PM>(ch, tb, sm.rec, sm.il_off, mv, 0, NG);
+        double f = m2p_far_part<GS, PM>(ch, tb, sm.rec, sm.il32, mv, 0, NG);
         f = wg_sum<NT>(f, sm.red);
         if (t == 0) {
           s_far = f;
@@ -1075,7 +1075,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
     __syncthreads();
     locate_move_par(ch, mv);
     __syncthreads();
-    double fsum = m2p_far_part<GS, PM>(ch, tb, sm.rec, sm.il_off, mv, (w - 1) * NG, (G - 1) * NG);
+    double fsum = m2p_far_part<GS, PM>(ch, tb, sm.rec, sm.il32, mv, (w - 1) * NG, (G - 1) * NG);
     fsum = wg_sum<NT>(fsum, sm.red);
     if (t == 0) {
       glb(ch.part)[w] = fsum;
