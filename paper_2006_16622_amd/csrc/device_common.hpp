@@ -260,14 +260,15 @@ __device__ __forceinline__ void mh_draw(uint64_t seed, uint64_t chain, uint64_t 
 // The loops are unrolled to PMAX so that the recurrence constants of the
 // column are all loaded before the dependent arithmetic starts.
 // rec layout: [0, Cs) A(n,m), [Cs, 2Cs) B(n,m) at slot(n,m); [2Cs, 2Cs+p] c_m.
-// lane i of a group receives the value of lane i - O (lanes below O keep
-// their own); DPP row shifts when a group is one 16-lane row
+// lane i of a group receives the value of lane i - O (lanes below O get
+// zero with DPP, their own value with the shuffle; scan_step discards it);
+// DPP row shifts when a group is one 16-lane row
 template <int GS, int O>
 __device__ __forceinline__ double shift_up(double v) {
   if constexpr (GS == 16) {
     int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x110 + O, 0xf, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x110 + O, 0xf, 0xf, false);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x110 + O, 0xf, 0xf, true);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x110 + O, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
   } else {
     return __shfl_up(v, O, GS);
@@ -278,7 +279,7 @@ template <int GS, int O>
 __device__ __forceinline__ float shift_up(float v) {
   if constexpr (GS == 16) {
     int b = __float_as_int(v);
-    b = __builtin_amdgcn_update_dpp(b, b, 0x110 + O, 0xf, 0xf, false);
+    b = __builtin_amdgcn_update_dpp(0, b, 0x110 + O, 0xf, 0xf, true);
     return __int_as_float(b);
   } else {
     return __shfl_up(v, O, GS);
