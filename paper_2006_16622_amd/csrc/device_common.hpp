@@ -566,20 +566,25 @@ __device__ __forceinline__ void p2l_sum(int lane, const P2LCols<PMAX, R> &cols, 
   }
 }
 
-// write a group's P2L column sums, times alpha_j, into the real-layout buffer
+// write a group's P2L column sums, times alpha_j, into the real-layout buffer.
+// No store is branched on: a row beyond p (and every row of a lane beyond p)
+// goes to a slot of the lane's own in `spare` (32 doubles, never read), and
+// the imaginary part is written before the real one, so that for m = 0 the
+// real part is the one that stays in the shared slot.
 template <int PMAX, typename P>
-__device__ __forceinline__ void flush_p2l(int lane, const Tabs &tb, const double *alpha, const ColSum<PMAX> &acc, P buf) {
+__device__ __forceinline__ void flush_p2l(int lane, const Tabs &tb, const double *alpha, const ColSum<PMAX> &acc, P buf,
+                                          double *spare) {
   const int p = tb.p, m = lane;
-  if (m > p) return;
 #pragma unroll
   for (int j = 0; j <= PMAX; ++j) {
     const int n = m + j;
-    if (n <= p) {
-      const int sp = n * n + n + m;
-      const double a = alpha[sp];
-      buf[sp] = a * acc.re[j];
-      if (m > 0) buf[n * n + n - m] = a * acc.im[j];
-    }
+    const bool valid = n <= p;
+    const int sp = valid ? n * n + n + m : 0;
+    const double a = alpha[sp];
+    double *pi = valid && m > 0 ? &buf[n * n + n - m] : spare + (lane & 15);
+    double *pr = valid ? &buf[sp] : spare + 16 + (lane & 15);
+    *pi = a * acc.im[j];
+    *pr = a * acc.re[j];
   }
 }
 

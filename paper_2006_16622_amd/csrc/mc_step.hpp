@@ -991,7 +991,7 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
       cand_pt(lst[1 + i], v[0], c[0]);
       p2l_sum<GS, PM, R, 1>(lane, cols, v, c, cs);
     }
-    flush_p2l<PM>(lane, tb, sm.p2la, cs, acc + (size_t)g * Cs);
+    flush_p2l<PM>(lane, tb, sm.p2la, cs, acc + (size_t)g * Cs, sm.red + 64);
     __syncthreads();
     for (int k = t; k < C; k += NT) {
       double sum = 0.0;
@@ -1032,7 +1032,7 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
     const R c[1] = {(R)it.q0};
     p2l_sum<GS, PM, R, 1>(lane, cols, v, c, cs);
   }
-  flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
+  flush_p2l<PM>(lane, tb, sm.p2la, cs, buf, sm.red + 64);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
@@ -1137,7 +1137,7 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
   // outstanding loads and stores, and waits for this row's stores before it
   // requests the next target's row.)
   auto finish_row = [&](gptr<double> dst, const double old[NJ], const ColSum<PM> &cs) __attribute__((always_inline)) {
-    flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
+    flush_p2l<PM>(lane, tb, sm.p2la, cs, buf, sm.red + 64);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
@@ -1162,7 +1162,7 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     ColSum<PM> cs;
     cs.zero();
     coarse_sum(2, s3, m, cs);
-    flush_p2l<PM>(lane, tb, sm.p2la, cs, buf);
+    flush_p2l<PM>(lane, tb, sm.p2la, cs, buf, sm.red + 64);
   }
   __syncthreads();
   if constexpr (!UNBRANCHED) {
