@@ -836,6 +836,10 @@ __device__ __forceinline__ FineItem fine_item(const Chain &ch, const Tabs &tb, c
   FineItem it;
   it.active = 0;
   it.two = 0;
+  // without a second point: a zero charge at unit distance (zero terms)
+  it.v1[0] = 1.0;
+  it.v1[1] = it.v1[2] = 0.0;
+  it.q1 = 0.0;
   const int n = fl.n;
   const int side = item >= 189, k189 = side ? item - 189 : item;
   int c[3], co[3], o[3];
@@ -1023,14 +1027,12 @@ __device__ __forceinline__ bool accept_block_compute(const Chain &ch, const Tabs
   load_p2l_cols<PM, R>(lane, tb, sm.p2lg, cols);
   ColSum<PM> cs;
   cs.zero();
-  if (it.two) {
+  {
+    // one pass for one or two points (a missing second point has zero
+    // charge), so that the lane groups of a wavefront do not branch apart
     const R v[2][3] = {{(R)it.v0[0], (R)it.v0[1], (R)it.v0[2]}, {(R)it.v1[0], (R)it.v1[1], (R)it.v1[2]}};
     const R c[2] = {(R)it.q0, (R)it.q1};
     p2l_sum<GS, PM, R, 2>(lane, cols, v, c, cs);
-  } else {
-    const R v[1][3] = {{(R)it.v0[0], (R)it.v0[1], (R)it.v0[2]}};
-    const R c[1] = {(R)it.q0};
-    p2l_sum<GS, PM, R, 1>(lane, cols, v, c, cs);
   }
   flush_p2l<PM>(lane, tb, sm.p2la, cs, buf, sm.red + 64);
   __builtin_amdgcn_wave_barrier();
@@ -1111,23 +1113,24 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     c = (R)(side ? mv.q : -mv.q);
   };
   // the terms of every candidate in mask m, two at a time (four at a time
-  // measured slower on one wavefront per SIMD)
+  // measured slower on one wavefront per SIMD); an odd last candidate is
+  // paired with a zero charge at unit distance, so that the lane groups of a
+  // wavefront run one pass
   auto coarse_sum = [&](int l, const int s3[3], uint64_t m, ColSum<PM> &cs) __attribute__((always_inline)) {
     while (m) {
       const int c0 = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
+      R v[2][3], q[2];
+      coarse_pt(l, s3, c0, v[0], q[0]);
       if (m) {
         const int c1 = __ffsll((unsigned long long)m) - 1;
         m &= m - 1;
-        R v[2][3], q[2];
-        coarse_pt(l, s3, c0, v[0], q[0]);
         coarse_pt(l, s3, c1, v[1], q[1]);
-        p2l_sum<GS, PM, R, 2>(lane, cols, v, q, cs);
       } else {
-        R v[1][3], q[1];
-        coarse_pt(l, s3, c0, v[0], q[0]);
-        p2l_sum<GS, PM, R, 1>(lane, cols, v, q, cs);
+        v[1][0] = R(1);
+        v[1][1] = v[1][2] = q[1] = R(0);
       }
+      p2l_sum<GS, PM, R, 2>(lane, cols, v, q, cs);
     }
   };
   // row := old + sums (old read slot by slot before the sums were formed,
@@ -1226,14 +1229,12 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     for (int j = 0; j < NJ; ++j) old[j] = dst[min(lane + j * GS, C - 1)];
     ColSum<PM> cs;
     cs.zero();
-    if (it.two) {
+    {
+      // one pass for one or two points, without a branch between the lane
+      // groups of a wavefront (a missing second point has zero charge)
       const R v[2][3] = {{(R)it.v0[0], (R)it.v0[1], (R)it.v0[2]}, {(R)it.v1[0], (R)it.v1[1], (R)it.v1[2]}};
       const R q[2] = {(R)it.q0, (R)it.q1};
       p2l_sum<GS, PM, R, 2>(lane, cols, v, q, cs);
-    } else {
-      const R v[1][3] = {{(R)it.v0[0], (R)it.v0[1], (R)it.v0[2]}};
-      const R q[1] = {(R)it.q0};
-      p2l_sum<GS, PM, R, 1>(lane, cols, v, q, cs);
     }
     finish_row(dst, old, cs);
   }
