@@ -588,12 +588,59 @@ __device__ __forceinline__ void flush_p2l(int lane, const Tabs &tb, const double
   }
 }
 
+// Butterfly all-reductions over aligned groups of W lanes (W = 16, 32, 64):
+// step o combines each lane with lane ^ o, o = W/2 .. 1. The steps across
+// 16-lane rows (32, 16) are shuffles; the steps inside a row are DPP row
+// rotations by o, a single instruction. After the steps above o every value
+// is unchanged under lane ^ o' for each o' > o inside the row, so the lane
+// that a rotation by o reaches holds the same value as lane ^ o: the sums
+// are those of the xor butterfly, bit for bit, in the same operand order.
+template <int O>
+__device__ __forceinline__ int row_ror(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + O, 0xf, 0xf, true);
+}
+template <int O>
+__device__ __forceinline__ double row_ror(double v) {
+  const int lo = row_ror<O>(__double2loint(v)), hi = row_ror<O>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+template <int W, int O, int K>
+__device__ __forceinline__ void sum_steps(double (&v)[K]) {
+  if constexpr (O >= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if constexpr (O >= 16)
+        v[k] += __shfl_xor(v[k], O, W);
+      else
+        v[k] += row_ror<O>(v[k]);
+    }
+    sum_steps<W, O / 2, K>(v);
+  }
+}
+// K values at once, their steps interleaved
+template <int W, int K>
+__device__ __forceinline__ void sum_allreduce(double (&v)[K]) {
+  sum_steps<W, W / 2, K>(v);
+}
+template <int W, int O>
+__device__ __forceinline__ unsigned or_steps(unsigned v) {
+  if constexpr (O >= 1) {
+    if constexpr (O >= 16)
+      v |= (unsigned)__shfl_xor((int)v, O, W);
+    else
+      v |= (unsigned)row_ror<O>((int)v);
+    return or_steps<W, O / 2>(v);
+  } else {
+    return v;
+  }
+}
+
 // sum over the GS lanes of a group (lanes of one wavefront)
 template <int GS>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GS);
-  return v;
+  double a[1] = {v};
+  sum_allreduce<GS, 1>(a);
+  return a[0];
 }
 
 // deterministic workgroup sum of four values at once: shuffle tree inside
@@ -601,10 +648,10 @@ __device__ __forceinline__ double group_sum(double v) {
 template <int NT>
 __device__ __forceinline__ void wg_sum4(double v[4], double *red) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double w[4] = {v[0], v[1], v[2], v[3]};
+  sum_allreduce<64, 4>(w);
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  for (int k = 0; k < 4; ++k) v[k] = w[k];
   if (lane == 0)
 #pragma unroll
     for (int k = 0; k < 4; ++k) red[4 * wv + k] = v[k];

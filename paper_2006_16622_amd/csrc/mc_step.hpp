@@ -615,8 +615,11 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
         self = q * q / sqrt(dx * dx + dy * dy + dz * dz);
       }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) self += __shfl_xor(self, o, 64);
+    {
+      double a[1] = {self};
+      sum_allreduce<64, 1>(a);
+      self = a[0];
+    }
   }
   __syncthreads();
 
@@ -676,14 +679,15 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
   if (singular) ints[I_SING] = 1;
   if (!gated && pt >= 2) dot(lv0);
   if (last_free && wv == NT / 64 - 1) spare(wl);
-  // wavefront partial sums (the shuffle trees of wg_sum4)
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    dold += __shfl_xor(dold, o, 64);
-    dnew += __shfl_xor(dnew, o, 64);
-    latq += __shfl_xor(latq, o, 64);
-    lato += __shfl_xor(lato, o, 64);
-    latn += __shfl_xor(latn, o, 64);
+  // wavefront partial sums (the butterflies of wg_sum4)
+  {
+    double a[5] = {dold, dnew, latq, lato, latn};
+    sum_allreduce<64, 5>(a);
+    dold = a[0];
+    dnew = a[1];
+    latq = a[2];
+    lato = a[3];
+    latn = a[4];
   }
   if (wl == 0) {
     sm.red[4 * wv + 0] = dold;
@@ -892,14 +896,8 @@ __device__ __forceinline__ uint64_t coarse_mask(const Move &mv, int l, const int
     }
     if (valid && mx >= 2) m |= 1ull << cand;
   }
-#pragma unroll
-  for (int o = GS / 2; o > 0; o >>= 1) {
-    unsigned lo = (unsigned)m, hi = (unsigned)(m >> 32);
-    lo |= __shfl_xor(lo, o, GS);
-    hi |= __shfl_xor(hi, o, GS);
-    m = (uint64_t)lo | ((uint64_t)hi << 32);
-  }
-  return m;
+  const unsigned lo = or_steps<GS, GS / 2>((unsigned)m), hi = or_steps<GS, GS / 2>((unsigned)(m >> 32));
+  return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 // The updated target rows of accept block blk of move mv, formed in LDS

@@ -928,8 +928,11 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
           double v = 0.0;
           if (ok)
             for (int hw = 1 + t; hw < G; hw += 64) v += glb(ch.part)[hw];
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+          {
+            double a[1] = {v};
+            sum_allreduce<64, 1>(a);
+            v = a[0];
+          }
           if (t == 0) {
             s_far = v;
             s_flag = ok ? 0 : 1;
