@@ -291,7 +291,18 @@ __device__ __forceinline__ void scan_step(int lane, R &wr, R &wi, R &s, bool irr
   if constexpr (O < GS) {
     R ur = shift_up<GS, O>(wr), ui = shift_up<GS, O>(wi);
     R us = irregular ? shift_up<GS, O>(s) : R(1);
-    if (lane >= O) {
+    if constexpr (GS == 16) {
+      // the DPP shift left zeros in the lanes below O: adding 1 to the real
+      // part there makes their factor the unit (1 + 0i, exact), so every
+      // lane multiplies and no result is selected (elsewhere + 0 is exact)
+      const R one = lane < O ? R(1) : R(0);
+      ur += one;
+      R nr = wr * ur - wi * ui;
+      R ni = wr * ui + wi * ur;
+      wr = nr;
+      wi = ni;
+      if (irregular) s *= us + one;
+    } else if (lane >= O) {
       R nr = wr * ur - wi * ui;
       R ni = wr * ui + wi * ur;
       wr = nr;
