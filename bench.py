@@ -65,11 +65,11 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "7d82b74e35dea251c5daa8411b7d873d2a65c996c5a813640d555a602ba07303",
-    "fetch_bytes_per_step": 784210.0,
+    "src_sha256": "6112d99901d5f0eb83daca8ff2678341ad6b418d8ebc9326069e629374575ed0",
+    "fetch_bytes_per_step": 781620.0,
     "write_bytes_per_step": 438489.0,
-    "batched_fetch_bytes_per_step": 209744.0,
-    "batched_write_bytes_per_step": 188498.0,
+    "batched_fetch_bytes_per_step": 209896.0,
+    "batched_write_bytes_per_step": 188492.0,
 }
 
 
