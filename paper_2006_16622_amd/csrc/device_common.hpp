@@ -261,8 +261,9 @@ __device__ __forceinline__ void mh_draw(uint64_t seed, uint64_t chain, uint64_t 
 // column are all loaded before the dependent arithmetic starts.
 // rec layout: [0, Cs) A(n,m), [Cs, 2Cs) B(n,m) at slot(n,m); [2Cs, 2Cs+p] c_m.
 // lane i of a group receives the value of lane i - O (lanes below O get
-// zero with DPP, their own value with the shuffle; scan_step discards it);
-// DPP row shifts when a group is one 16-lane row
+// zero with DPP, which scan_step turns into the unit factor, and their own
+// value with the shuffle, which it discards); DPP row shifts when a group
+// is one 16-lane row
 template <int GS, int O>
 __device__ __forceinline__ double shift_up(double v) {
   if constexpr (GS == 16) {
@@ -654,7 +655,7 @@ __device__ __forceinline__ double group_sum(double v) {
   return a[0];
 }
 
-// deterministic workgroup sum of four values at once: shuffle tree inside
+// deterministic workgroup sum of four values at once: a butterfly inside
 // each wavefront, then the NT/64 wave totals in order; red: 16 doubles of LDS
 template <int NT>
 __device__ __forceinline__ void wg_sum4(double v[4], double *red) {

@@ -505,7 +505,7 @@ __device__ __forceinline__ void group_harmonics_store(int lane, const Tabs &tb, 
 //   6. lane 0 of the last wavefront adds the wavefront sums in order,
 //      assembles dE and calls decide(dE, singular); a last barrier makes
 //      the decision visible.
-// The sums are shuffle trees inside each wavefront, then the wavefront
+// The sums are butterflies inside each wavefront, then the wavefront
 // totals in order, as in propose_wg; the lattice values are summed the same
 // way here (group sums there), so dE agrees with propose_wg to rounding.
 template <int GS, int PM, typename R, int NT, typename Early, typename Spare, typename Gate, typename Decide>
