@@ -1210,16 +1210,26 @@ __device__ __forceinline__ void accept_all_wg(const Chain &ch, const Tabs &tb, c
     }
   }
   // ---- levels >= 4: one or two terms per item's own target
-  const int nfine = L >= 4 ? (L - 3) * 378 : 0;
-  int fl_l = 0;  // the level whose shared quantities fl holds
+  // On a level where r and r' share their cell the two interaction lists
+  // coincide and every new-side item belongs to the old side: such a level
+  // contributes its 189 old-side items only.
+  auto level_items = [&](int l) __attribute__((always_inline)) {
+    const bool same = mv.c0[l][0] == mv.c1[l][0] && mv.c0[l][1] == mv.c1[l][1] && mv.c0[l][2] == mv.c1[l][2];
+    return same ? 189 : 378;
+  };
+  int nfine = 0;
+  for (int l = 4; l <= L; ++l) nfine += level_items(l);
+  int fl_l = 4, fl_base = 0, fl_n = L >= 4 ? level_items(4) : 0;  // level of fl, its first index, its items
   FineLevel fl;
+  if (L >= 4) fl = fine_level(ch, mv, 4);
   for (int i = g; i < nfine; i += NG) {
-    const int l = 4 + i / 378;
-    if (l != fl_l) {
-      fl = fine_level(ch, mv, l);
-      fl_l = l;
+    while (i - fl_base >= fl_n) {  // the items of the next level (uniform over the group)
+      fl_base += fl_n;
+      ++fl_l;
+      fl_n = level_items(fl_l);
+      fl = fine_level(ch, mv, fl_l);
     }
-    const FineItem it = fine_item(ch, tb, sm.il32, mv, fl, i - (l - 4) * 378);
+    const FineItem it = fine_item(ch, tb, sm.il32, mv, fl, i - fl_base);
     if (!it.active) continue;
     const auto dst = glb(it.dst);
     double old[NJ];
