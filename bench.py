@@ -65,11 +65,11 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "684b0b8b0ba4131b7f677c8f201511abd49b4e0a824aa1d020992358259adbf5",
-    "fetch_bytes_per_step": 781620.0,
+    "src_sha256": "cfe21e7a43113bb0b0de5193be35e2c188ed6446422378f82307f4dcef880dc4",
+    "fetch_bytes_per_step": 784124.0,
     "write_bytes_per_step": 438489.0,
-    "batched_fetch_bytes_per_step": 209896.0,
-    "batched_write_bytes_per_step": 188492.0,
+    "batched_fetch_bytes_per_step": 210007.0,
+    "batched_write_bytes_per_step": 188495.0,
 }
 
 
