@@ -310,11 +310,34 @@ __device__ __forceinline__ bool spin_all_equal(unsigned *flags, int G, unsigned 
   }
 }
 
+// The order in which the H helpers of the whole-GPU run take the nblk accept
+// blocks: helper w takes the positions w - 1, w - 1 + H, ... The 8 level-2
+// cells come first, then the fine-level blocks, with 8 level-3 cells placed
+// at positions H .. H + 7 and the other level-3 cells last; a helper that
+// holds a level-2 cell (the heaviest block) thus takes a level-3 cell (the
+// lightest) next, where in block order it would take a fine block. Without
+// fine blocks the order is the block order. Returns the block at position v.
+__host__ __device__ inline int block_at(int v, int H, int nblk) {
+  if (v < 8 || nblk <= 72) return v;
+  const int F = nblk - 72;                              // fine blocks
+  const int A = H - 8 < 0 ? 0 : (H - 8 > F ? F : H - 8);  // fine blocks before the 8 level-3 cells
+  if (v < 8 + A) return 72 + (v - 8);
+  if (v < 16 + A) return 8 + (v - 8 - A);
+  if (v < 16 + F) return 72 + (v - 16);
+  return 16 + (v - 16 - F);
+}
+// the helper (1 .. H) that holds fine block b >= 72
+__host__ __device__ inline int helper_of_fine(int b, int H, int nblk) {
+  const int F = nblk - 72, f = b - 72;
+  const int A = H - 8 < 0 ? 0 : (H - 8 > F ? F : H - 8);
+  return 1 + (f < A ? 8 + f : 16 + f) % H;
+}
+
 // a helper's wait before it reads target rows: wavefront 0 polls the done
 // flags of the helpers holding fine-level blocks (levels 4..L, bpl blocks
-// each; block b belongs to helper 1 + b % (G - 1)) of the levels in `lvmask`
+// each; fine block b belongs to helper_of_fine(b)) of the levels in `lvmask`
 // until all have reached `target` (a flag may already be past it)
-__device__ __forceinline__ bool spin_level_helpers(unsigned *flags, int G, unsigned lvmask, int bpl,
+__device__ __forceinline__ bool spin_level_helpers(unsigned *flags, int G, int nblk, unsigned lvmask, int bpl,
                                                    unsigned target, uint64_t limit) {
   const int lane = threadIdx.x & 63;
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
@@ -324,7 +347,7 @@ __device__ __forceinline__ bool spin_level_helpers(unsigned *flags, int G, unsig
       if (!((lvmask >> l) & 1u)) continue;
       const int b0 = 72 + (l - 4) * bpl;
       for (int b = b0 + lane; b < b0 + bpl; b += 64)
-        mine = mine && ((int)(ld_relaxed(&flags[1 + b % (G - 1)]) - target) >= 0);
+        mine = mine && ((int)(ld_relaxed(&flags[helper_of_fine(b, G - 1, nblk)]) - target) >= 0);
     }
     if (__all(mine)) return true;
     if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
@@ -688,7 +711,8 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
     }
     return;
   }
-  // ---- helper workgroups: block k of this helper (blocks w-1, w-1+G-1, ...)
+  // ---- helper workgroups: block k of this helper (positions w-1, w-1+G-1, ...
+  // of block_at's order)
   // forms its rows in spec(k): the group buffers for k = 0, then the dynamic
   // LDS after the standard layout; then the row pointers of all its blocks
   const int kmax = (nblk + G - 2) / (G - 1);  // blocks of the busiest helper
@@ -705,8 +729,10 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
   // helper, which stores and re-reads them itself)
   const int bpl = (378 + NG - 1) / NG;
   unsigned lvmask = 0;
-  for (int b = w - 1; b < nblk; b += G - 1)
+  for (int v = w - 1; v < nblk; v += G - 1) {
+    const int b = block_at(v, G - 1, nblk);
     if (b >= 72) lvmask |= 1u << (4 + (b - 72) / bpl);
+  }
   while (true) {
     const unsigned num = cur + 1;
     // wait until move `num` is posted; the stop flag is stored before the
@@ -751,7 +777,7 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
     // accepted move, stored by the helpers of those levels, must be in place
     if (confirmed != last_acc && lvmask) {
       if (t < 64) {
-        bool ok = spin_level_helpers(doneflag, G, lvmask, bpl, last_acc, SPIN_LIMIT);
+        bool ok = spin_level_helpers(doneflag, G, nblk, lvmask, bpl, last_acc, SPIN_LIMIT);
         if (t == 0) s_flag = ok ? 0 : 1;
       }
       __syncthreads();
@@ -767,8 +793,9 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
     locate_move_par(ch, mv);
     __syncthreads();
     // speculation: the updated rows of every own block, in LDS
-    for (int k = 0, b = w - 1; b < nblk; ++k, b += G - 1) {
-      bool coarse = accept_block_compute<GS, PM, R>(ch, tb, mv, b, sm, spec(k), sdst + (size_t)k * NG);
+    for (int k = 0, v = w - 1; v < nblk; ++k, v += G - 1) {
+      bool coarse =
+          accept_block_compute<GS, PM, R>(ch, tb, mv, block_at(v, G - 1, nblk), sm, spec(k), sdst + (size_t)k * NG);
       if (t == 0) s_coarse[k] = coarse;
       __syncthreads();
     }
@@ -807,7 +834,7 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
     }
     if (res == 3) return;
     if (res == 1) {
-      for (int k = 0, b = w - 1; b < nblk; ++k, b += G - 1)
+      for (int k = 0, v = w - 1; v < nblk; ++k, v += G - 1)
         accept_block_store<GS, NT>(tb, s_coarse[k], spec(k), sdst + (size_t)k * NG);
       // The rows are agent-scope atomic stores, which write through this
       // XCD's L2; once they have completed (the wait below) they are
