@@ -311,15 +311,36 @@ __device__ __forceinline__ bool spin_all_equal(unsigned *flags, int G, unsigned 
 }
 
 // The order in which the H helpers of the whole-GPU run take the nblk accept
-// blocks: helper w takes the positions w - 1, w - 1 + H, ... The 8 level-2
-// cells come first, then the fine-level blocks, with 8 level-3 cells placed
-// at positions H .. H + 7 and the other level-3 cells last; a helper that
-// holds a level-2 cell (the heaviest block) thus takes a level-3 cell (the
-// lightest) next, where in block order it would take a fine block. Without
-// fine blocks the order is the block order. Returns the block at position v.
-__host__ __device__ inline int block_at(int v, int H, int nblk) {
+// blocks: helper w takes the positions w - 1, w - 1 + H, ... The blocks
+// differ in weight: a level-2 cell has some 47 candidate terms, a level-3
+// cell a few, and a fine block of bpl blocks per level holds its level's
+// old-side items (its first jh blocks, two terms per active item) or
+// new-side ones (mostly owned by the old side, when r and r' share a cell).
+// With two blocks per helper (nblk = 2 H) the first H positions hold the
+// level-2 cells, the old-side fine blocks and level-3 cells, the second H the
+// level-3 cells that pair with the level-2 ones, the new-side fine blocks
+// that pair with the old-side ones, and the other level-3 cells. Otherwise
+// the level-2 cells come first, then the fine blocks with 8 level-3 cells at
+// positions H .. H + 7 (the second block of a level-2 holder), then the other
+// level-3 cells. Without fine blocks the order is the block order.
+// Returns the block at position v.
+__host__ __device__ inline int block_at(int v, int H, int nblk, int bpl, int jh) {
   if (v < 8 || nblk <= 72) return v;
-  const int F = nblk - 72;                              // fine blocks
+  const int F = nblk - 72;  // fine blocks: F / bpl levels, jh old-side blocks on each
+  if (2 * H == nblk) {
+    const int Fh = F / bpl * jh, Fl = F - Fh, x = H - 8 - Fh;
+    if (v < 8 + Fh) {
+      const int i = v - 8;
+      return 72 + i / jh * bpl + i % jh;
+    }
+    if (v < H) return 16 + (v - 8 - Fh);
+    if (v < H + 8) return 8 + (v - H);
+    if (v < H + 8 + Fl) {
+      const int i = v - H - 8, nl = bpl - jh;
+      return 72 + i / nl * bpl + jh + i % nl;
+    }
+    return 16 + x + (v - H - 8 - Fl);
+  }
   const int A = H - 8 < 0 ? 0 : (H - 8 > F ? F : H - 8);  // fine blocks before the 8 level-3 cells
   if (v < 8 + A) return 72 + (v - 8);
   if (v < 16 + A) return 8 + (v - 8 - A);
@@ -327,17 +348,24 @@ __host__ __device__ inline int block_at(int v, int H, int nblk) {
   return 16 + (v - 16 - F);
 }
 // the helper (1 .. H) that holds fine block b >= 72
-__host__ __device__ inline int helper_of_fine(int b, int H, int nblk) {
+__host__ __device__ inline int helper_of_fine(int b, int H, int nblk, int bpl, int jh) {
   const int F = nblk - 72, f = b - 72;
-  const int A = H - 8 < 0 ? 0 : (H - 8 > F ? F : H - 8);
-  return 1 + (f < A ? 8 + f : 16 + f) % H;
+  int v;
+  if (2 * H == nblk) {
+    const int li = f / bpl, j = f % bpl;
+    v = j < jh ? 8 + li * jh + j : H + 8 + li * (bpl - jh) + (j - jh);
+  } else {
+    const int A = H - 8 < 0 ? 0 : (H - 8 > F ? F : H - 8);
+    v = f < A ? 8 + f : 16 + f;
+  }
+  return 1 + v % H;
 }
 
 // a helper's wait before it reads target rows: wavefront 0 polls the done
 // flags of the helpers holding fine-level blocks (levels 4..L, bpl blocks
 // each; fine block b belongs to helper_of_fine(b)) of the levels in `lvmask`
 // until all have reached `target` (a flag may already be past it)
-__device__ __forceinline__ bool spin_level_helpers(unsigned *flags, int G, int nblk, unsigned lvmask, int bpl,
+__device__ __forceinline__ bool spin_level_helpers(unsigned *flags, int G, int nblk, unsigned lvmask, int bpl, int jh,
                                                    unsigned target, uint64_t limit) {
   const int lane = threadIdx.x & 63;
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
@@ -347,7 +375,7 @@ __device__ __forceinline__ bool spin_level_helpers(unsigned *flags, int G, int n
       if (!((lvmask >> l) & 1u)) continue;
       const int b0 = 72 + (l - 4) * bpl;
       for (int b = b0 + lane; b < b0 + bpl; b += 64)
-        mine = mine && ((int)(ld_relaxed(&flags[helper_of_fine(b, G - 1, nblk)]) - target) >= 0);
+        mine = mine && ((int)(ld_relaxed(&flags[helper_of_fine(b, G - 1, nblk, bpl, jh)]) - target) >= 0);
     }
     if (__all(mine)) return true;
     if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
@@ -728,9 +756,10 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
   // to move (the coarse blocks of levels 2 and 3 always belong to the same
   // helper, which stores and re-reads them itself)
   const int bpl = (378 + NG - 1) / NG;
+  const int jh = (189 + NG - 1) / NG;  // the blocks of a level holding its old-side items
   unsigned lvmask = 0;
   for (int v = w - 1; v < nblk; v += G - 1) {
-    const int b = block_at(v, G - 1, nblk);
+    const int b = block_at(v, G - 1, nblk, bpl, jh);
     if (b >= 72) lvmask |= 1u << (4 + (b - 72) / bpl);
   }
   while (true) {
@@ -777,7 +806,7 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
     // accepted move, stored by the helpers of those levels, must be in place
     if (confirmed != last_acc && lvmask) {
       if (t < 64) {
-        bool ok = spin_level_helpers(doneflag, G, nblk, lvmask, bpl, last_acc, SPIN_LIMIT);
+        bool ok = spin_level_helpers(doneflag, G, nblk, lvmask, bpl, jh, last_acc, SPIN_LIMIT);
         if (t == 0) s_flag = ok ? 0 : 1;
       }
       __syncthreads();
@@ -795,7 +824,7 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
     // speculation: the updated rows of every own block, in LDS
     for (int k = 0, v = w - 1; v < nblk; ++k, v += G - 1) {
       bool coarse =
-          accept_block_compute<GS, PM, R>(ch, tb, mv, block_at(v, G - 1, nblk), sm, spec(k), sdst + (size_t)k * NG);
+          accept_block_compute<GS, PM, R>(ch, tb, mv, block_at(v, G - 1, nblk, bpl, jh), sm, spec(k), sdst + (size_t)k * NG);
       if (t == 0) s_coarse[k] = coarse;
       __syncthreads();
     }
