@@ -302,8 +302,16 @@ __device__ __forceinline__ bool spin_all_equal(unsigned *flags, int G, unsigned 
   const int lane = threadIdx.x & 63;
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   while (true) {
-    bool mine = true;
-    for (int w = 1 + lane; w < G; w += 64) mine = mine && (ld_relaxed(&flags[w]) == target);
+    // the first four flags of this lane are all requested before any is
+    // compared, so a poll whose flags are already set takes one round trip
+    unsigned v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int w = 1 + lane + 64 * i;
+      v[i] = w < G ? ld_relaxed(&flags[w]) : target;
+    }
+    bool mine = v[0] == target && v[1] == target && v[2] == target && v[3] == target;
+    for (int w = 257 + lane; w < G; w += 64) mine = mine && (ld_relaxed(&flags[w]) == target);
     if (__all(mine)) return true;
     if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return false;
     __builtin_amdgcn_s_sleep(1);
