@@ -65,11 +65,11 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "1acd7ce8c345288b8b273f2c45c0c5f26d9bc1244d6d0b409c709c4f9dbec5cb",
-    "fetch_bytes_per_step": 779707.2,
+    "src_sha256": "d03ee3cd712ddb1a3b6a798e72f1e683dae6d5fd1bce99abe42af2be118fc306",
+    "fetch_bytes_per_step": 779779.0,
     "write_bytes_per_step": 438489.2,
-    "batched_fetch_bytes_per_step": 210005.9,
-    "batched_write_bytes_per_step": 188495.5,
+    "batched_fetch_bytes_per_step": 210002.6,
+    "batched_write_bytes_per_step": 188497.1,
 }
 
 
