@@ -561,22 +561,23 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
   }
 
   // ---- 2. the harmonics of every point; early(); the self-image terms
-  double hh = 1.0, *buf = nullptr;
+  double ihh = 1.0, *buf = nullptr;  // ihh: 1 / (side of the point's cell)
   const double *src = nullptr;
   if (pt >= 0) {
     double x[3];
     if (pt < 2) {
       buf = pt ? sm.latN : sm.latO;
       const double *r = pt ? mv.rn : mv.r;
-      hh = a;
-      for (int k = 0; k < 3; ++k) x[k] = (r[k] - 0.5 * a) / a;
+      ihh = 1.0 / a;
+      for (int k = 0; k < 3; ++k) x[k] = (r[k] - 0.5 * a) * ihh;
     } else {
       const int l = 2 + (pt - 2) / 2, sd = (pt - 2) % 2, n = 1 << (l - 1);
       buf = sm.gbuf + (size_t)g * Cs;
-      hh = a / n;
+      const double hh = a / n;
+      ihh = n / a;
       const int *c = sd ? mv.c1[l] : mv.c0[l];
       const double *r = sd ? mv.rn : mv.r;
-      for (int k = 0; k < 3; ++k) x[k] = (r[k] - (c[k] + 0.5) * hh) / hh;
+      for (int k = 0; k < 3; ++k) x[k] = (r[k] - (c[k] + 0.5) * hh) * ihh;
       src = ch.Ld + ch.ld_off[l] + (size_t)lin3(n, c[0], c[1], c[2]) * Cs;
     }
     if (pt < 2 || sizeof(R) == 8)  // the lattice term is FP64 in every mode
@@ -596,7 +597,7 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
       acc += s2 < C ? term : 0.0;
     }
     acc = group_sum<GS>(acc);
-    if (lane == 0) sm.vals[pt] = acc / hh;
+    if (lane == 0) sm.vals[pt] = acc * ihh;
   };
   double self = 0.0;  // the last wavefront: sum of the self-image terms
   if (wv == NT / 64 - 1) {
@@ -729,17 +730,18 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
     dE += q * (part[1] - part[0]);
     dE += -part[2];
     if (!ch.free_space) {
-      dE += q * q / a * tb.self_const;
+      const double ia = 1.0 / a;  // one division; the terms below multiply by it
+      dE += q * q * ia * tb.self_const;
       double vo = 0.0, vn = 0.0;
       for (int w2 = 0; w2 < NT / 64; ++w2) {
         vo += sm.red[16 + 2 * w2];
         vn += sm.red[17 + 2 * w2];
       }
-      dE += q * (vn / a - vo / a) + 0.5 * part[3] / a;
+      dE += q * (vn * ia - vo * ia) + 0.5 * part[3] * ia;
       const double dr[3] = {mv.rn[0] - mv.r[0], mv.rn[1] - mv.r[1], mv.rn[2] - mv.r[2]};
       const double Ddot = sm.st[0] * dr[0] + sm.st[1] * dr[1] + sm.st[2] * dr[2];
       const double dd = dr[0] * dr[0] + dr[1] * dr[1] + dr[2] * dr[2];
-      dE += -2.0 * M_PI / (3.0 * a * a * a) * (2.0 * q * Ddot + q * q * dd);
+      dE += -(2.0 * M_PI / 3.0) * (ia * ia * ia) * (2.0 * q * Ddot + q * q * dd);
     } else if (!(mv.rn[0] >= 0.0 && mv.rn[0] < a && mv.rn[1] >= 0.0 && mv.rn[1] < a && mv.rn[2] >= 0.0 &&
                  mv.rn[2] < a)) {
       dE = INFINITY;  // free space: a move out of the box is never taken
