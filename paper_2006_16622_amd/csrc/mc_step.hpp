@@ -672,8 +672,8 @@ __device__ __forceinline__ void propose_fast(const Chain &ch, const Tabs &tb, co
       double v;
       if constexpr (sizeof(R) == 4)
         v = pj.w * (double)rsqrtf((float)r2);  // FP32 inverse distance of an FP64 difference
-      else
-        v = pj.w / sqrt(r2);
+      else  // 1/r by the refined estimate; r = 0 gives the infinity a division would
+        v = pj.w * (r2 > 0.0 ? rsqrt_nr(r2) : INFINITY);
       if (side) dnew += v; else dold += v;
     }
   }
