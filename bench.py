@@ -65,11 +65,11 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "d03ee3cd712ddb1a3b6a798e72f1e683dae6d5fd1bce99abe42af2be118fc306",
-    "fetch_bytes_per_step": 779779.0,
+    "src_sha256": "c7e7ce52a0af86d81b4340c4703cef9f9f62a330ab0e32bcaf5598b17526ee50",
+    "fetch_bytes_per_step": 779878.2,
     "write_bytes_per_step": 438489.2,
-    "batched_fetch_bytes_per_step": 210002.6,
-    "batched_write_bytes_per_step": 188497.1,
+    "batched_fetch_bytes_per_step": 209992.2,
+    "batched_write_bytes_per_step": 188496.0,
 }
 
 
