@@ -65,11 +65,11 @@ P_GATE = 19  # smallest degree whose rock-salt dE error against Ewald is below 1
 # on the acceptance rate, which the fixed proposal stream fixes. Valid only
 # for the kernel sources they were taken on; otherwise the traffic is null.
 MEASURED_TRAFFIC = {
-    "src_sha256": "c7e7ce52a0af86d81b4340c4703cef9f9f62a330ab0e32bcaf5598b17526ee50",
-    "fetch_bytes_per_step": 779878.2,
+    "src_sha256": "e36957b51de27a8391df6eba80827545b50f28cb760ebcab00b9f763ab320f8f",
+    "fetch_bytes_per_step": 779828.9,
     "write_bytes_per_step": 438489.2,
-    "batched_fetch_bytes_per_step": 209992.2,
-    "batched_write_bytes_per_step": 188496.0,
+    "batched_fetch_bytes_per_step": 209943.4,
+    "batched_write_bytes_per_step": 188496.3,
 }
 
 

@@ -149,6 +149,14 @@ __device__ __forceinline__ void move_from_draw(const RunParams &rp, const Chain 
 
 // one workgroup per CU is the shape of the batched launch (256 chains), so
 // a workgroup may use the whole register file (2 wavefronts per SIMD)
+// The Metropolis test u < exp(-beta dE), u in [0, 1). With beta > 0 a move
+// with dE <= 0 passes it whatever u is (exp(-beta dE) >= 1 > u), so the
+// exponential is formed only for the others; every decision is the one
+// the comparison itself gives.
+__device__ __forceinline__ bool mh_accept(double u, double beta, double dE) {
+  return (beta > 0.0 && dE <= 0.0) || u < exp(-beta * dE);
+}
+
 template <int GS, int PM, typename R, bool MP = false>
 __global__ void __launch_bounds__(WG_BATCH) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
@@ -199,7 +207,7 @@ k_run_batched(const Chain *chains, Tabs tb, RunParams rp) {
     uint64_t t_1 = __builtin_amdgcn_s_memrealtime();
     tick_prop += t_1 - t_0;
     if (t == 0) {
-      int acc = !po.singular && (u < exp(-rp.beta * po.dE));
+      int acc = !po.singular && mh_accept(u, rp.beta, po.dE);
       // a move that would overflow its new leaf bin is not taken: the chain
       // stops with the error and its state is that before the move
       s_ovf = acc && move_overflows(ch, mv, sm.ints);
@@ -601,7 +609,7 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
             },
             gate,
             [&](double dE, int sing) {  // one thread (lane 0 of the last wavefront)
-              int acc = !sing && (mc.u < exp(-rp.beta * dE));
+              int acc = !sing && mh_accept(mc.u, rp.beta, dE);
               // a move that would overflow its new leaf bin is published as
               // rejected (the helpers drop its rows) and the chain stops
               s_ovf = acc && move_overflows(ch, mc, sm.ints);
@@ -636,7 +644,7 @@ __device__ __forceinline__ void run_chain_wg(const Chain &ch_arg, const Tabs &tb
             },
             gate);
         if (t == 0) {
-          int acc = !po.singular && (u < exp(-rp.beta * po.dE));
+          int acc = !po.singular && mh_accept(u, rp.beta, po.dE);
           s_ovf = acc && move_overflows(ch, mv, sm.ints);
           if (s_ovf) acc = 0;
           s_acc = acc;
@@ -1022,7 +1030,7 @@ __global__ void __launch_bounds__(WG_SINGLE) k_run_single_mp(Chain ch_arg, Tabs 
       tick_prop += t_w - t_0;
       tick_wait += t_1 - t_w;
       if (t == 0) {
-        int acc = !po.singular && (u < exp(-rp.beta * dE));
+        int acc = !po.singular && mh_accept(u, rp.beta, dE);
         s_ovf = acc && move_overflows(ch, mv, sm.ints);
         if (s_ovf) acc = 0;
         s_acc = acc;
